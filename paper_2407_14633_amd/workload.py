@@ -1,0 +1,321 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module builds *inputs only*: tight-binding ring blocks of zigzag carbon
+nanotubes, lead descriptions, on-site potential profiles, quadrature nodes and
+weights for the energy integrals, and bias points.  It holds none of the
+Green's-function arithmetic (no inversion, no self-energy, no Fermi factor);
+both the CPU oracle and the HIP library receive the arrays built here.
+
+Conventions
+-----------
+* A device has ``N`` rings of ``b`` atoms; atom ``i`` of ring ``j`` has flat
+  index ``j*b + i``.  ``h_diag[j]`` is the on-site block ``H_{j,j}`` (potential
+  excluded), ``h_up[j] = H_{j,j+1}``; ``H_{j+1,j} = h_up[j]^H``.
+* A lead is a semi-infinite, periodic continuation of the ring chain, listed
+  *outward* from the device: lead ring 0 touches the device, ring 1 is next,
+  and so on.  ``period`` rings form one unit cell; ``h_diag[r]`` is the block of
+  lead ring r, ``h_up[r] = H_{ring r, ring r+1}`` (for r = period-1 it couples
+  to ring 0 of the next cell), and ``tau = H_{device edge ring, lead ring 0}``.
+* Zigzag (n,0) nanotube (the paper's material, Section 3.1: (17,0) tube with a
+  2.5 eV nearest-neighbour coupling): rings carry no intra-ring bond, and ring
+  couplings alternate between a two-bond block ``t (I + S^T)`` and a one-bond
+  block ``t I``, ``S`` being the cyclic shift of the ring.  Ring ``j``'s outgoing
+  coupling is the two-bond one for even ``j``.
+* Energies are in eV.  Quadrature weights include the Jacobian ``dE/dx``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+T_CC = -2.5          # nearest-neighbour pz coupling (eV), Section 3.1
+KT_300K = 0.0259     # kT at room temperature (eV)
+FERMI_TAIL = 14.0    # f1 = f2 = 14, Eq. 4
+
+
+# --------------------------------------------------------------------------
+# Containers
+# --------------------------------------------------------------------------
+@dataclass
+class Lead:
+    period: int
+    h_diag: np.ndarray        # (period, b, b) complex128
+    h_up: np.ndarray          # (period, b, b) complex128
+    tau: np.ndarray           # (b, b) complex128
+
+
+@dataclass
+class Device:
+    h_diag: np.ndarray        # (N, b, b) complex128
+    h_up: np.ndarray          # (N-1, b, b) complex128
+    left: Lead
+    right: Lead
+
+    @property
+    def n_rings(self) -> int:
+        return self.h_diag.shape[0]
+
+    @property
+    def b(self) -> int:
+        return self.h_diag.shape[1]
+
+
+@dataclass
+class Bias:
+    mu_L: float
+    mu_R: float
+    kT_L: float = KT_300K
+    kT_R: float = KT_300K
+
+
+@dataclass
+class EnergyGrid:
+    z_c: np.ndarray           # (n_c,) complex contour nodes
+    w_c: np.ndarray           # (n_c,) complex weights (dz Jacobian x Gauss weight)
+    E_r: np.ndarray           # (n_r,) real-axis nodes
+    w_r: np.ndarray           # (n_r,) real weights
+
+    @property
+    def n_c(self) -> int:
+        return int(self.z_c.shape[0])
+
+    @property
+    def n_r(self) -> int:
+        return int(self.E_r.shape[0])
+
+
+@dataclass
+class Problem:
+    """One complete solve: device, potential, bias, energy grid, options."""
+    name: str
+    device: Device
+    U: np.ndarray             # (N*b,) per-atom potential energy (eV)
+    U_left: float
+    U_right: float
+    bias: Bias
+    grid: EnergyGrid
+    eta: float = 1e-6
+    decim_tol: float = 1e-12
+    decim_max_iter: int = 64
+    g_s: float = 2.0
+    meta: dict = field(default_factory=dict)
+
+
+# --------------------------------------------------------------------------
+# Zigzag nanotube Hamiltonian blocks
+# --------------------------------------------------------------------------
+def ring_shift(n: int) -> np.ndarray:
+    """Cyclic shift S with S[i, (i+1) mod n] = 1."""
+    S = np.zeros((n, n))
+    S[np.arange(n), (np.arange(n) + 1) % n] = 1.0
+    return S
+
+
+def zigzag_coupling(n: int, j: int, t: float = T_CC) -> np.ndarray:
+    """H_{j,j+1} of a zigzag (n,0) tube: two bonds per atom for even j, one for odd j."""
+    if j % 2 == 0:
+        return (t * (np.eye(n) + ring_shift(n).T)).astype(np.complex128)
+    return (t * np.eye(n)).astype(np.complex128)
+
+
+def zigzag_cnt(n: int, N: int, t: float = T_CC) -> Device:
+    """Device of N rings of an (n,0) tube with leads that continue the ring parity."""
+    if N < 1 or n < 1:
+        raise ValueError("need n >= 1 atoms per ring and N >= 1 rings")
+    h_diag = np.zeros((N, n, n), np.complex128)
+    h_up = np.stack([zigzag_coupling(n, j, t) for j in range(N - 1)]) if N > 1 \
+        else np.zeros((0, n, n), np.complex128)
+    # right lead: device ring N + r is lead ring r
+    right = Lead(period=2,
+                 h_diag=np.zeros((2, n, n), np.complex128),
+                 h_up=np.stack([zigzag_coupling(n, N, t), zigzag_coupling(n, N + 1, t)]),
+                 tau=zigzag_coupling(n, N - 1, t))
+    # left lead: device ring -1 - r is lead ring r; H_{-1-r,-2-r} = H_{-2-r,-1-r}^H
+    left = Lead(period=2,
+                h_diag=np.zeros((2, n, n), np.complex128),
+                h_up=np.stack([zigzag_coupling(n, -2, t).conj().T,
+                               zigzag_coupling(n, -3, t).conj().T]),
+                tau=zigzag_coupling(n, -1, t).conj().T)
+    return Device(h_diag=h_diag, h_up=h_up, left=left, right=right)
+
+
+def random_device(N: int, b: int, seed: int, period: int = 1, scale: float = 1.0,
+                  complex_couplings: bool = True) -> Device:
+    """A generic Hermitian block-tridiagonal device with random periodic leads.
+
+    Used for brute-force checks on tiny systems: nothing in it is nanotube-specific.
+    """
+    rng = np.random.default_rng(seed)
+
+    def herm(m):
+        a = rng.normal(size=(m, m)) + (1j * rng.normal(size=(m, m)) if complex_couplings else 0)
+        return (scale * 0.5 * (a + a.conj().T)).astype(np.complex128)
+
+    def gen(m):
+        a = rng.normal(size=(m, m)) + (1j * rng.normal(size=(m, m)) if complex_couplings else 0)
+        return (scale * a).astype(np.complex128)
+
+    def lead():
+        return Lead(period=period,
+                    h_diag=np.stack([herm(b) for _ in range(period)]),
+                    h_up=np.stack([gen(b) for _ in range(period)]),
+                    tau=gen(b))
+
+    h_diag = np.stack([herm(b) for _ in range(N)])
+    h_up = np.stack([gen(b) for _ in range(N - 1)]) if N > 1 else np.zeros((0, b, b), np.complex128)
+    return Device(h_diag=h_diag, h_up=h_up, left=lead(), right=lead())
+
+
+def gershgorin_lower(dev: Device, U: np.ndarray) -> float:
+    """Lower Gershgorin bound of the device plus leads (used to start the contour)."""
+    N, b = dev.n_rings, dev.b
+    diag = np.real(np.einsum("jii->ji", dev.h_diag)).reshape(-1) + U
+    off = np.abs(dev.h_diag).sum(axis=2).reshape(-1) - np.abs(np.einsum("jii->ji", dev.h_diag)).reshape(-1)
+    for j in range(N - 1):
+        off[j * b:(j + 1) * b] += np.abs(dev.h_up[j]).sum(axis=1)
+        off[(j + 1) * b:(j + 2) * b] += np.abs(dev.h_up[j]).sum(axis=0)
+    off[:b] += np.abs(dev.left.tau).sum(axis=1)
+    off[(N - 1) * b:] += np.abs(dev.right.tau).sum(axis=1)
+    rows = diag - off
+    lo = rows.min()
+    for ld in (dev.left, dev.right):
+        for r in range(ld.period):
+            d = np.real(np.diag(ld.h_diag[r]))
+            o = np.abs(ld.h_diag[r]).sum(axis=1) - np.abs(np.diag(ld.h_diag[r]))
+            o = o + np.abs(ld.h_up[r]).sum(axis=1) + np.abs(ld.h_up[r - 1]).sum(axis=0)
+            if r == 0:
+                o = o + np.abs(ld.tau).sum(axis=0)
+            lo = min(lo, (d - o).min())
+    return float(lo)
+
+
+# --------------------------------------------------------------------------
+# Potential profiles (per atom, eV)
+# --------------------------------------------------------------------------
+def potential_smooth_ring(N: int, b: int, amplitude: float, seed: int) -> np.ndarray:
+    """Ring-uniform smooth profile that vanishes at both contacts.
+
+    s_j = sum_{m=1..4} (a_m/m) sin(pi m (j+1)/(N+1)), a_m ~ U(-1,1);
+    U_j = amplitude * s_j / max|s|.
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, size=4)
+    j = np.arange(N)
+    s = sum((a[m - 1] / m) * np.sin(np.pi * m * (j + 1) / (N + 1)) for m in range(1, 5))
+    s = amplitude * s / np.max(np.abs(s))
+    return np.repeat(s, b).astype(np.float64)
+
+
+def potential_tanh_barrier(N: int, b: int, seed: int, height_range=(0.2, 0.5),
+                           width: float = 10.0, noise: float = 0.01) -> tuple[np.ndarray, float]:
+    """Gate-like barrier between N/4 and 3N/4 plus per-atom Gaussian noise.
+
+    U_{j,i} = U_b/2 [tanh((j - N/4)/w) - tanh((j - 3N/4)/w)] + N(0, noise^2).
+    Returns (U, U_b).
+    """
+    rng = np.random.default_rng(seed)
+    Ub = float(rng.uniform(*height_range))
+    j = np.arange(N, dtype=np.float64)
+    prof = 0.5 * Ub * (np.tanh((j - N / 4) / width) - np.tanh((j - 3 * N / 4) / width))
+    U = np.repeat(prof, b) + rng.normal(0.0, noise, size=N * b)
+    return U.astype(np.float64), Ub
+
+
+# --------------------------------------------------------------------------
+# Quadrature grids
+# --------------------------------------------------------------------------
+def gauss_legendre(n: int) -> tuple[np.ndarray, np.ndarray]:
+    x, w = np.polynomial.legendre.leggauss(n)
+    return x, w
+
+
+def real_axis_gl(E_lo: float, E_hi: float, n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Gauss-Legendre nodes/weights on [E_lo, E_hi]."""
+    if n == 0:
+        return np.zeros(0), np.zeros(0)
+    x, w = gauss_legendre(n)
+    half, mid = 0.5 * (E_hi - E_lo), 0.5 * (E_hi + E_lo)
+    return mid + half * x, half * w
+
+
+def real_axis_midpoint(E_lo: float, E_hi: float, n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Uniform midpoint rule on [E_lo, E_hi]."""
+    h = (E_hi - E_lo) / n
+    return E_lo + (np.arange(n) + 0.5) * h, np.full(n, h)
+
+
+def semicircle_contour(E_b: float, E_top: float, n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Gauss-Legendre rule on the upper semicircle from E_b to E_top.
+
+    z(theta) = c + R exp(i theta), c = (E_b+E_top)/2, R = (E_top-E_b)/2, theta in (0, pi).
+    Returned weights w_k integrate f along the path from E_b to E_top:
+    sum_k w_k f(z_k) ~ int_{E_b}^{E_top} f dz, i.e. w_k = -i R e^{i theta_k} (pi/2) omega_k.
+    """
+    if n == 0:
+        return np.zeros(0, np.complex128), np.zeros(0, np.complex128)
+    x, w = gauss_legendre(n)
+    c, R = 0.5 * (E_b + E_top), 0.5 * (E_top - E_b)
+    th = 0.5 * np.pi * (x + 1.0)
+    z = c + R * np.exp(1j * th)
+    wz = -1j * R * np.exp(1j * th) * (0.5 * np.pi) * w
+    return z.astype(np.complex128), wz.astype(np.complex128)
+
+
+def window(bias: Bias, tail: float = FERMI_TAIL) -> tuple[float, float]:
+    """(E_min, E_max) of Eq. 4: mu_min - f1 kT_min, mu_max + f2 kT_max."""
+    E_min = min(bias.mu_L, bias.mu_R) - tail * min(bias.kT_L, bias.kT_R)
+    E_max = max(bias.mu_L, bias.mu_R) + tail * max(bias.kT_L, bias.kT_R)
+    return E_min, E_max
+
+
+def nonequilibrium_grid(E_b: float, bias: Bias, n_c: int, n_r: int,
+                        tail: float = FERMI_TAIL) -> EnergyGrid:
+    """Contour part on [E_b, E_min] plus Gauss-Legendre real axis on [E_min, E_max]."""
+    E_min, E_max = window(bias, tail)
+    z_c, w_c = semicircle_contour(E_b, E_min, n_c)
+    E_r, w_r = real_axis_gl(E_min, E_max, n_r)
+    return EnergyGrid(z_c, w_c, E_r, w_r)
+
+
+# --------------------------------------------------------------------------
+# The workloads
+# --------------------------------------------------------------------------
+def small_problem(seed: int = 1234) -> Problem:
+    """(8,0) tube, 64 rings, smooth ring-uniform potential in [-0.3,0.3] eV,
+    256 uniform real-axis energies in [-1,1] eV, V = 0.1 V, kT = 0.0259 eV."""
+    n, N = 8, 64
+    dev = zigzag_cnt(n, N)
+    U = potential_smooth_ring(N, n, 0.3, seed)
+    E, w = real_axis_midpoint(-1.0, 1.0, 256)
+    grid = EnergyGrid(np.zeros(0, np.complex128), np.zeros(0, np.complex128), E, w)
+    bias = Bias(mu_L=0.05, mu_R=-0.05)
+    return Problem("cnt8_N64_real256", dev, U, 0.0, 0.0, bias, grid,
+                   meta=dict(n=n, N=N, seed=seed))
+
+
+def device_problem(N: int = 400, n: int = 17, seed: int = 2024, n_c: int = 512,
+                   n_r: int = 1536, V: float = 0.3) -> Problem:
+    """(17,0) tube with a tanh gate barrier, 512 contour + 1536 real-axis points,
+    source/drain mu = +/- V/2 (default +/-0.15 eV)."""
+    dev = zigzag_cnt(n, N)
+    U, Ub = potential_tanh_barrier(N, n, seed)
+    bias = Bias(mu_L=0.5 * V, mu_R=-0.5 * V)
+    E_b = gershgorin_lower(dev, U) - 1.0
+    grid = nonequilibrium_grid(E_b, bias, n_c, n_r)
+    return Problem(f"cnt{n}_N{N}_c{n_c}_r{n_r}", dev, U, 0.0, 0.0, bias, grid,
+                   meta=dict(n=n, N=N, seed=seed, U_b=Ub, E_b=E_b))
+
+
+def subsample_grid(grid: EnergyGrid, n_c: int, n_r: int, seed: int) -> EnergyGrid:
+    """A fixed random subset of a grid's nodes (weights kept as they are)."""
+    rng = np.random.default_rng(seed)
+    ic = np.sort(rng.choice(grid.n_c, size=min(n_c, grid.n_c), replace=False)) if grid.n_c else np.zeros(0, int)
+    ir = np.sort(rng.choice(grid.n_r, size=min(n_r, grid.n_r), replace=False)) if grid.n_r else np.zeros(0, int)
+    return EnergyGrid(grid.z_c[ic], grid.w_c[ic], grid.E_r[ir], grid.w_r[ir])
+
+
+def with_grid(p: Problem, grid: EnergyGrid, name: Optional[str] = None) -> Problem:
+    return Problem(name or p.name + "_sub", p.device, p.U, p.U_left, p.U_right, p.bias, grid,
+                   p.eta, p.decim_tol, p.decim_max_iter, p.g_s, dict(p.meta))
