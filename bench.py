@@ -1,0 +1,206 @@
+"""Energy-point solve throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload device|small|device1000|device2000]
+                    [--no-cpu-baseline] [--no-fp32]
+
+One step = one full negf_solve_dev (decimation, both recursions, contour diagonals,
+lead columns, energy sums) over the workload's energy grid, inputs already in HBM.
+Prints one JSON line on stdout; per-kernel details go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2407_14633_amd import workload as W  # noqa: E402
+
+METRIC = "RGF energy-point solves/sec (FP64 vs FP32-bulk) + p50/p99 I-V request latency"
+FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
+FP32_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_problem(name: str) -> W.Problem:
+    if name == "device":
+        return W.device_problem(N=400)
+    if name == "device1000":
+        return W.device_problem(N=1000)
+    if name == "device2000":
+        return W.device_problem(N=2000)
+    if name == "small":
+        return W.small_problem()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def ell_width(dev: W.Device) -> int:
+    K = 1
+    for H in dev.h_up:
+        nz = np.abs(H) > 0
+        K = max(K, int(nz.sum(axis=0).max()), int(nz.sum(axis=1).max()))
+    return K
+
+
+def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
+    """Real flops per kernel launch, from the method's operation counts.
+
+    Counting: a b x b complex Gauss-Jordan inverse = b^3 complex multiply-adds = 8 b^3
+    flops; a dense b x b complex product = 8 b^3; an ELL product of width K = 8 b^2 K.
+    """
+    N, b = p.device.n_rings, p.device.b
+    K = ell_width(p.device)
+    n_c, n_r = p.grid.n_c, p.grid.n_r
+    inv, mul, ell = 8.0 * b ** 3, 8.0 * b ** 3, 8.0 * b * b * K
+    # recursions: N-1 steps of (inverse + 2 ELL products) per chain, plus the final
+    # inverse on real-axis chains; two chains per node
+    recur = 2 * (n_c + n_r) * (N - 1) * (inv + 2 * ell) + 2 * n_r * inv
+    cdiag = n_c * N * inv
+    # lead columns: per ring one propagation product and one W Gamma product (+ b^2 dots)
+    column = 2 * n_r * (N * (mul + 8.0 * b * b) + (N - 1) * mul)
+    # decimation: per doubling step (period 2) 4 inverses + 14 products; final 2 inverses + 4 products
+    per_it = {1: 1 * inv + 6 * mul, 2: 4 * inv + 14 * mul}
+    fin = {1: inv + 2 * mul, 2: 2 * inv + 4 * mul}
+    dec = 0.0
+    for l, ld in enumerate((p.device.left, p.device.right)):
+        dec += per_it[ld.period] * float(decim_iters[:, l].sum()) + fin[ld.period] * len(decim_iters)
+    return {"recur": recur, "cdiag": cdiag, "column": column, "decimate": dec}
+
+
+def cpu_baseline(p: W.Problem, n_c: int = 8, n_r: int = 24, seed: int = 99) -> dict:
+    """The oracle as it stands, timed on the host cores over a fixed sample of nodes."""
+    from concurrent.futures import ProcessPoolExecutor
+    cores = min(os.cpu_count() or 1, 16, n_c + n_r)
+    sub = W.subsample_grid(p.grid, n_c, n_r, seed)
+    jobs = [("c", z) for z in sub.z_c] + [("r", E) for E in sub.E_r]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(_oracle_point, [(p, kind, x) for kind, x in jobs]))
+    dt = time.perf_counter() - t0
+    return {"value": len(jobs) / dt, "unit": "energy-point solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sub.n_c} contour + {sub.n_r} real-axis nodes of the same workload (seed {seed}), "
+                      f"numpy/LAPACK oracle incl. decimation, one process per core, {dt:.2f} s wall"}
+
+
+def _oracle_point(args):
+    from oracle import negf_oracle as O
+    p, kind, x = args
+    if kind == "c":
+        return O.energy_point_contour(p, x)
+    return O.energy_point_real(p, x)
+
+
+def run(p: W.Problem, precision: int, steps: int, warmup: int):
+    import torch
+    from paper_2407_14633_amd import negf
+    dev = torch.device("cuda:0")
+    d = negf.NegfDevice(p.device, precision=precision, eta=p.eta, decim_tol=p.decim_tol,
+                        decim_max_iter=p.decim_max_iter, g_s=p.g_s)
+    d.set_potential(p.U, p.U_left, p.U_right)
+    g = p.grid
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype=dt)
+    zc = t(g.z_c.view(np.float64).reshape(-1, 2), torch.float64) if g.n_c else None
+    wc = t(g.w_c.view(np.float64).reshape(-1, 2), torch.float64) if g.n_c else None
+    Er = t(g.E_r, torch.float64) if g.n_r else None
+    wr = t(g.w_r, torch.float64) if g.n_r else None
+    nb = p.device.n_rings * p.device.b
+    charge = torch.zeros(nb, dtype=torch.float64, device=dev)
+    T = torch.zeros(max(g.n_r, 1), dtype=torch.float64, device=dev)
+    cur = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        d.solve_dev(p.bias, zc, wc, Er, wr, charge, T, cur, stream)
+    d.sync()
+    d.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        d.solve_dev(p.bias, zc, wc, Er, wr, charge, T, cur, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    d.sync()
+    times = d.kernel_times()
+    d.set_profiling(False)
+    # one detailed host solve for the decimation step counts (not timed)
+    res = d.solve(p.bias, p.grid, details=True)
+    out = dict(ms_per_step=1e3 * dt / steps, times=times, iters=res.decim_iters,
+               charge=charge.cpu().numpy(), current=float(cur.item()))
+    d.close()
+    return out
+
+
+def roofline(p, r, peak_tflops):
+    flops = algorithmic_flops(p, r["iters"])
+    best = None
+    for k, (ms, calls) in r["times"].items():
+        if k in flops and calls:
+            avg = ms / calls
+            if best is None or avg > best[1]:
+                best = (k, avg)
+    k, avg = best
+    ach = flops[k] / (avg * 1e-3) / 1e12
+    return {"kernel": k, "bound": "alu", "achieved": round(ach, 4), "peak": peak_tflops, "unit": "TFLOP/s",
+            "frac": round(ach / peak_tflops, 5), "traffic": None, "avg_ms": round(avg, 4),
+            "flops_per_launch": flops[k]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="device")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the energy-point solve on a single MI355X "
+              "(energy nodes would shard across GPUs with one all-reduce of the charge; not built here).",
+              file=sys.stderr)
+        raise SystemExit(2)
+    from paper_2407_14633_amd import negf
+    p = make_problem(a.workload)
+    n_e = p.grid.n_c + p.grid.n_r
+    log(f"workload {p.name}: N={p.device.n_rings} b={p.device.b} n_c={p.grid.n_c} n_r={p.grid.n_r}")
+    # the oracle's worker processes are forked before anything touches the GPU
+    cpu = None if a.no_cpu_baseline else cpu_baseline(p)
+    log("cpu baseline", cpu)
+    r64 = run(p, negf.FP64, a.steps, a.warmup)
+    log("fp64 ms/step", r64["ms_per_step"], "kernels", r64["times"])
+    rf64 = roofline(p, r64, FP64_PEAK_TFLOPS)
+    log("fp64 roofline", rf64)
+    fp32 = None
+    if not a.no_fp32:
+        r32 = run(p, negf.FP32_BULK, a.steps, a.warmup)
+        log("fp32-bulk ms/step", r32["ms_per_step"], "kernels", r32["times"])
+        rf32 = roofline(p, r32, FP32_PEAK_TFLOPS)
+        err = float(np.max(np.abs(r32["charge"] - r64["charge"])) / np.max(np.abs(r64["charge"])))
+        fp32 = {"value": n_e / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
+                "roofline": rf32, "charge_rel_diff_vs_fp64": err,
+                "current_rel_diff_vs_fp64": abs(r32["current"] - r64["current"]) / abs(r64["current"] or 1.0)}
+    line = {
+        "metric": METRIC, "value": n_e / (r64["ms_per_step"] * 1e-3), "unit": "energy-point solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{p.name}: zigzag (17,0) CNT tight binding, {p.device.n_rings} rings, "
+                               f"{p.grid.n_c} contour + {p.grid.n_r} real-axis nodes, mu = +/-0.15 eV, eta 1e-6",
+                   "n_rings": p.device.n_rings, "ring_size": p.device.b, "n_contour": p.grid.n_c,
+                   "n_real": p.grid.n_r},
+        "roofline": rf64, "cpu_baseline": cpu, "fp32_bulk": fp32,
+        "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in r64["times"].items()},
+        "serving": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

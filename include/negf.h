@@ -1,0 +1,174 @@
+/*
+ * negf.h -- C ABI of the MI355X energy-point Green's-function engine.
+ *
+ * The library solves, for a batch of energy nodes, the non-equilibrium Green's
+ * function problem of a block-tridiagonal tight-binding device coupled to two
+ * semi-infinite leads (paper Section 2.2.1, Eq. 2-5):
+ *
+ *   G^R(z) = [ z I - H - diag(U) - Sigma_L(z) - Sigma_R(z) ]^{-1}          (Eq. 2)
+ *   Sigma_l = tau_l g_l tau_l^H,  g_l by Sancho-Rubio decimation           (Eq. 2)
+ *   Gamma_l = i (Sigma_l - Sigma_l^H),  A_l = G Gamma_l G^H                 (Eq. 3)
+ *   charge_i = g_s [ -(1/pi) sum_c Im(w_c F_min(z_c) G^R_ii(z_c))
+ *                   + (1/2pi) sum_r w_r (f_L A_L,ii + f_R A_R,ii)(E_r) ]  (Eq. 4)
+ *   T_LR(E)  = Tr[Gamma_L G Gamma_R G^H]                                   (Eq. 5)
+ *   current  = g_s (e^2/h) sum_r w_r T_LR(E_r) (f_L - f_R)(E_r)            (Eq. 5, Landauer form)
+ *
+ * Units: energies in eV, current in A.  `charge` is an electron count per atom
+ * including spin; the paper's density is rho = -e * charge.
+ *
+ * Layouts: complex values are interleaved {re, im} doubles (the layout of
+ * std::complex<double> and torch.complex128).  Matrices are row-major.  Atom i
+ * of ring j has flat index j*b + i.
+ *
+ * Ownership: create/set_potential copy their inputs; callers keep their arrays.
+ * Output arrays are caller-allocated.  A handle runs one solve at a time and is
+ * not thread-safe; separate handles are independent.
+ *
+ * Errors: every call returns a negf_status; negf_last_error() gives a
+ * thread-local message for the last non-OK status.  On error no output is
+ * guaranteed to have been written.
+ */
+#ifndef NEGF_H
+#define NEGF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct negf_device negf_device;
+typedef struct { double re, im; } negf_c64;
+
+typedef enum {
+    NEGF_OK = 0,
+    NEGF_EINVAL = -1,     /* bad size, NULL pointer, unsupported ring size  */
+    NEGF_ENOMEM = -2,     /* device memory allocation failed               */
+    NEGF_ENOCONV = -3,    /* decimation did not converge in decim_max_iter */
+    NEGF_ESINGULAR = -4,  /* non-finite pivot or output                    */
+    NEGF_EHIP = -5        /* HIP runtime error                             */
+} negf_status;
+
+enum { NEGF_FP64 = 0, NEGF_FP32_BULK = 1 };
+enum { NEGF_LEAD_LEFT = 0, NEGF_LEAD_RIGHT = 1 };
+enum { NEGF_MAX_RING = 24, NEGF_MAX_PERIOD = 2 };
+
+/*
+ * A semi-infinite lead as a periodic continuation of the ring chain, listed
+ * outward from the device (lead ring 0 touches the device).  `period` rings
+ * (1 or 2) form the principal layer of the decimation (Section 2.2.2).
+ *   h_diag[period][b][b]  on-site blocks of the lead rings (lead potential excluded)
+ *   h_up  [period][b][b]  h_up[r] = H_{ring r, ring r+1}; h_up[period-1] couples to
+ *                         ring 0 of the next cell
+ *   tau   [b][b]          H_{device edge ring, lead ring 0}; Sigma = tau g_00 tau^H
+ */
+typedef struct {
+    int period;
+    const negf_c64 *h_diag;
+    const negf_c64 *h_up;
+    const negf_c64 *tau;
+} negf_lead;
+
+typedef struct {
+    int precision;            /* NEGF_FP64, or NEGF_FP32_BULK: recursions and block
+                                 products in complex FP32; decimation and the energy
+                                 sums stay FP64                                      */
+    double eta;               /* i*eta added to real-axis nodes (device and leads)   */
+    double decim_tol;         /* stop when max |alpha_ij|, |beta_ij| < decim_tol (eV) */
+    int decim_max_iter;       /* NEGF_ENOCONV beyond this many doubling steps        */
+    double g_s;               /* spin degeneracy (2)                                 */
+    size_t workspace_bytes;   /* cap on the per-energy recursion store; 0 = default  */
+} negf_options;
+
+typedef struct { double mu_L, mu_R, kT_L, kT_R; } negf_bias;
+
+/* Optional energy-resolved outputs of negf_solve_ex (host pointers; NULL = skip). */
+typedef struct {
+    double   *charge;       /* [N*b]                                              */
+    double   *T;            /* [n_r]    T_LR at the real-axis nodes               */
+    double   *current;      /* [1]                                                */
+    negf_c64 *gr_diag;      /* [n_c][N*b]  diag G^R at the contour nodes          */
+    double   *al_diag;      /* [n_r][N*b]  diag A_L at the real-axis nodes        */
+    double   *ar_diag;      /* [n_r][N*b]  diag A_R at the real-axis nodes        */
+    int      *decim_iters;  /* [n_c+n_r][2] doubling steps taken, left and right  */
+} negf_outputs;
+
+/* Fills *opt with eta=1e-6, decim_tol=1e-12, decim_max_iter=64, g_s=2, FP64. */
+void negf_default_options(negf_options *opt);
+
+/*
+ * Creates a device handle on the current HIP device and copies the Hamiltonian
+ * to HBM (Eq. 2: block-tridiagonal H).
+ *   n_rings >= 1, 1 <= b <= NEGF_MAX_RING
+ *   h_diag [n_rings][b][b]  H_{j,j}, potential excluded
+ *   h_up   [n_rings-1][b][b] H_{j,j+1}; H_{j+1,j} = h_up^H (may be NULL if n_rings == 1)
+ * The potential starts at zero.  EINVAL on bad sizes/NULLs, ENOMEM, EHIP.
+ */
+negf_status negf_create_device(negf_device **out, int n_rings, int b,
+                               const negf_c64 *h_diag, const negf_c64 *h_up,
+                               const negf_lead *left, const negf_lead *right,
+                               const negf_options *opt);
+
+/* Sets the on-site potential energy: U[N*b] per atom (eV, added to H_jj's diagonal)
+ * and the flat lead potentials U_left, U_right (added to the lead rings). */
+negf_status negf_set_potential(negf_device *d, const double *U, double U_left, double U_right);
+
+/* Device-pointer form of negf_set_potential; U is read on `hip_stream`. */
+negf_status negf_set_potential_dev(negf_device *d, const double *U_dev, double U_left,
+                                   double U_right, void *hip_stream);
+
+/*
+ * One solve over n_c contour nodes and n_r real-axis nodes (host pointers),
+ * synchronous.  z_c/w_c: contour nodes and complex quadrature weights (dz Jacobian
+ * included, Fermi factor NOT included: the library applies F(z - mu_min; kT_min)).
+ * E_r/w_r: real nodes (i*eta added inside) and weights.  Outputs: charge[N*b],
+ * T[n_r] (may be NULL), current[1] (may be NULL).
+ */
+negf_status negf_solve(negf_device *d, const negf_bias *bias,
+                       int n_c, const negf_c64 *z_c, const negf_c64 *w_c,
+                       int n_r, const double *E_r, const double *w_r,
+                       double *charge, double *T, double *current);
+
+/* negf_solve with the optional energy-resolved outputs of negf_outputs. */
+negf_status negf_solve_ex(negf_device *d, const negf_bias *bias,
+                          int n_c, const negf_c64 *z_c, const negf_c64 *w_c,
+                          int n_r, const double *E_r, const double *w_r,
+                          const negf_outputs *out);
+
+/*
+ * Asynchronous solve with every array in device memory, enqueued on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns after enqueueing; the status
+ * of the device-side checks (decimation convergence, finite outputs) is returned
+ * by negf_sync().  T and current may be NULL.
+ */
+negf_status negf_solve_dev(negf_device *d, const negf_bias *bias,
+                           int n_c, const negf_c64 *z_c, const negf_c64 *w_c,
+                           int n_r, const double *E_r, const double *w_r,
+                           double *charge, double *T, double *current, void *hip_stream);
+
+/* Waits for the last negf_solve_dev and returns its device-side status. */
+negf_status negf_sync(negf_device *d);
+
+/*
+ * Lead self-energies alone (decimation, Eq. 2), host pointers, synchronous:
+ * sigma[n][b][b] = Sigma_lead(z[k]), iters[n] = doubling steps (may be NULL).
+ * Contour-style nodes: z is used as given (no eta is added).
+ */
+negf_status negf_lead_self_energy(negf_device *d, int lead, int n, const negf_c64 *z,
+                                  negf_c64 *sigma, int *iters);
+
+/* Per-kernel GPU time (ms) accumulated since the last reset when profiling is on:
+ * names[k] / ms[k] for k < *count (count in: capacity, out: entries). */
+negf_status negf_set_profiling(negf_device *d, int enable);
+negf_status negf_kernel_times(negf_device *d, const char **names, double *ms, int *calls, int *count);
+
+/* Device memory held by the handle (bytes). */
+size_t negf_device_bytes(const negf_device *d);
+
+void negf_destroy(negf_device *d);
+const char *negf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEGF_H */

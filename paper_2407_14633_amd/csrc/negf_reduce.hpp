@@ -1,0 +1,142 @@
+// Energy-sum kernels (Eq. 4-5) and small helpers; used by the C-ABI unit only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "negf_kernels.hpp"
+
+namespace negf {
+
+// ============================================================ reductions ==
+struct RedArgs {
+    int Nb, n_c, n_r;
+    double g_s;
+    double mu_L, mu_R, kT_L, kT_R;
+    const cx<double>* z_c;     // [n_c]
+    const cx<double>* w_c;     // [n_c]
+    const double* E_r;         // [n_r]
+    const double* w_r;         // [n_r]
+    cx<double>* coef_c;        // [n_c]   w_c F(z_c - mu_min; kT_min)
+    double* coef_r;            // [n_r][3] w fL, w fR, w (fL - fR)
+    const void* gr_diag;       // [n_c][Nb] cx<T>
+    const void* a_diag;        // [n_r][2][Nb] T
+    const double* T;           // [n_r]
+    double* charge;            // [Nb]
+    double* current;           // [1] or null
+    int* flags;                // [1] bit 2: non-finite output
+};
+
+__device__ __forceinline__ double fermi_real(double E, double mu, double kT) {
+    const double x = (E - mu) / kT;
+    if (x > 0) { const double e = exp(-x); return e / (1.0 + e); }
+    return 1.0 / (1.0 + exp(x));
+}
+
+__device__ __forceinline__ cx<double> fermi_cplx(cx<double> z, double mu, double kT) {
+    // 1/(1 + exp(u)), u = (z - mu)/kT, evaluated through exp(-u) when Re u > 0
+    const double ur = (z.re - mu) / kT, ui = z.im / kT;
+    const bool pos = ur > 0;
+    const double m = exp(pos ? -ur : ur);
+    const double c = m * cos(pos ? -ui : ui), s = m * sin(pos ? -ui : ui);   // e = exp(+-u)
+    const double dr = 1.0 + c, di = s;                                      // 1 + e
+    const double den = dr * dr + di * di;
+    // pos: F = e / (1 + e);  else: F = 1 / (1 + e)
+    const double nr = pos ? c : 1.0, ni = pos ? s : 0.0;
+    return cx<double>{(nr * dr + ni * di) / den, (ni * dr - nr * di) / den};
+}
+
+__global__ void k_coef(RedArgs R) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const double mu_min = fmin(R.mu_L, R.mu_R), kT_min = fmin(R.kT_L, R.kT_R);
+    if (e < R.n_c) {
+        const cx<double> F = fermi_cplx(R.z_c[e], mu_min, kT_min);
+        const cx<double> w = R.w_c[e];
+        R.coef_c[e] = cx<double>{w.re * F.re - w.im * F.im, w.re * F.im + w.im * F.re};
+    } else if (e < R.n_c + R.n_r) {
+        const int q = e - R.n_c;
+        const double fl = fermi_real(R.E_r[q], R.mu_L, R.kT_L);
+        const double fr = fermi_real(R.E_r[q], R.mu_R, R.kT_R);
+        const double w = R.w_r[q];
+        R.coef_r[3 * q + 0] = w * fl;
+        R.coef_r[3 * q + 1] = w * fr;
+        R.coef_r[3 * q + 2] = w * (fl - fr);
+    }
+}
+
+// charge_i in two fixed-order passes: energy segment `seg` (a fixed split of the
+// node index range) is summed in index order into part[seg][i], then the
+// segments are added in order.  The result depends only on the node list.
+constexpr int RED_SEGS = 32;
+
+template <typename T>
+__global__ void k_reduce_part(RedArgs R, double* part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int seg = blockIdx.y;
+    if (i >= R.Nb) return;
+    const int ne = R.n_c + R.n_r;
+    const int e_lo = (int)(((long long)ne * seg) / RED_SEGS), e_hi = (int)(((long long)ne * (seg + 1)) / RED_SEGS);
+    double acc_c = 0.0, acc_r = 0.0;
+    const cx<T>* gr = reinterpret_cast<const cx<T>*>(R.gr_diag);
+    const T* ad = reinterpret_cast<const T*>(R.a_diag);
+    for (int e = e_lo; e < e_hi; ++e) {
+        if (e < R.n_c) {
+            const cx<T> gv = gr[(size_t)e * R.Nb + i];
+            const cx<double> w = R.coef_c[e];
+            acc_c += w.re * (double)gv.im + w.im * (double)gv.re;    // Im(w G)
+        } else {
+            const int q = e - R.n_c;
+            const double al = (double)ad[((size_t)q * 2 + 0) * R.Nb + i];
+            const double ar = (double)ad[((size_t)q * 2 + 1) * R.Nb + i];
+            acc_r += R.coef_r[3 * q + 0] * al + R.coef_r[3 * q + 1] * ar;
+        }
+    }
+    const double inv_pi = 0.31830988618379067154;
+    part[(size_t)seg * R.Nb + i] = -inv_pi * acc_c + 0.5 * inv_pi * acc_r;
+}
+
+__global__ void k_reduce_final(RedArgs R, const double* part) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R.Nb) return;
+    double acc = 0.0;
+    for (int seg = 0; seg < RED_SEGS; ++seg) acc += part[(size_t)seg * R.Nb + i];
+    const double ch = R.g_s * acc;
+    R.charge[i] = ch;
+    if (!isfinite(ch)) atomicOr(R.flags, 2);
+}
+
+// current: one wavefront, lane l sums nodes l, l+64, ... then a fixed tree
+__global__ __launch_bounds__(64) void k_current(RedArgs R) {
+    __shared__ double red[64];
+    const int l = threadIdx.x;
+    double acc = 0.0;
+    for (int q = l; q < R.n_r; q += 64) acc += R.coef_r[3 * q + 2] * R.T[q];
+    red[l] = acc;
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+        if (l < s) red[l] += red[l + s];
+        __syncthreads();
+    }
+    if (l == 0) {
+        const double G0 = 1.602176634e-19 * 1.602176634e-19 / 6.62607015e-34;   // e^2/h
+        const double cur = R.g_s * G0 * red[0];
+        if (R.current) *R.current = cur;
+        if (!isfinite(cur)) atomicOr(R.flags, 2);
+    }
+}
+
+// prepares the node array: contour nodes as given, real nodes E + i eta
+__global__ void k_nodes(const cx<double>* z_c, int n_c, const double* E_r, int n_r, double eta, cx<double>* z) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_c) z[e] = z_c[e];
+    else if (e < n_c + n_r) z[e] = cx<double>{E_r[e - n_c], eta};
+}
+
+// folds per-energy decimation status into the flag word
+__global__ void k_status(const int* status, int n, int* flags, int* first_bad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n && status[e]) {
+        atomicOr(flags, status[e]);
+        atomicMin(first_bad, e);
+    }
+}
+
+}  // namespace negf

@@ -1,0 +1,256 @@
+"""ctypes binding of libnegf.so (include/negf.h): argument marshalling only.
+
+Every step of a solve runs in the library's HIP kernels; this module converts
+numpy arrays / torch tensors to pointers and status codes to exceptions.  It
+raises if the library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from .workload import Bias, Device, EnergyGrid, Lead, Problem
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnegf.so")
+
+NEGF_OK, NEGF_EINVAL, NEGF_ENOMEM, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_EHIP = 0, -1, -2, -3, -4, -5
+FP64, FP32_BULK = 0, 1
+STATUS_NAMES = {0: "NEGF_OK", -1: "NEGF_EINVAL", -2: "NEGF_ENOMEM", -3: "NEGF_ENOCONV",
+                -4: "NEGF_ESINGULAR", -5: "NEGF_EHIP"}
+
+EXPORTED = [
+    "negf_default_options", "negf_create_device", "negf_set_potential", "negf_set_potential_dev",
+    "negf_solve", "negf_solve_ex", "negf_solve_dev", "negf_sync", "negf_lead_self_energy",
+    "negf_set_profiling", "negf_kernel_times", "negf_device_bytes", "negf_destroy", "negf_last_error",
+]
+
+
+class NegfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class c64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class negf_lead(C.Structure):
+    _fields_ = [("period", C.c_int), ("h_diag", C.c_void_p), ("h_up", C.c_void_p), ("tau", C.c_void_p)]
+
+
+class negf_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("eta", C.c_double), ("decim_tol", C.c_double),
+                ("decim_max_iter", C.c_int), ("g_s", C.c_double), ("workspace_bytes", C.c_size_t)]
+
+
+class negf_bias(C.Structure):
+    _fields_ = [("mu_L", C.c_double), ("mu_R", C.c_double), ("kT_L", C.c_double), ("kT_R", C.c_double)]
+
+
+class negf_outputs(C.Structure):
+    _fields_ = [("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p), ("gr_diag", C.c_void_p),
+                ("al_diag", C.c_void_p), ("ar_diag", C.c_void_p), ("decim_iters", C.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libnegf.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2407_14633_amd.build`")
+    lib = C.CDLL(path)
+    vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    lib.negf_default_options.argtypes = [C.POINTER(negf_options)]
+    lib.negf_default_options.restype = None
+    lib.negf_create_device.argtypes = [C.POINTER(vp), i, i, vp, vp, C.POINTER(negf_lead), C.POINTER(negf_lead),
+                                       C.POINTER(negf_options)]
+    lib.negf_set_potential.argtypes = [vp, vp, d, d]
+    lib.negf_set_potential_dev.argtypes = [vp, vp, d, d, vp]
+    lib.negf_solve.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp]
+    lib.negf_solve_ex.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, C.POINTER(negf_outputs)]
+    lib.negf_solve_dev.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
+    lib.negf_sync.argtypes = [vp]
+    lib.negf_lead_self_energy.argtypes = [vp, i, i, vp, vp, vp]
+    lib.negf_set_profiling.argtypes = [vp, i]
+    lib.negf_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(d), C.POINTER(i), C.POINTER(i)]
+    lib.negf_device_bytes.argtypes = [vp]
+    lib.negf_device_bytes.restype = sz
+    lib.negf_destroy.argtypes = [vp]
+    lib.negf_destroy.restype = None
+    lib.negf_last_error.argtypes = []
+    lib.negf_last_error.restype = C.c_char_p
+    for name in ("negf_create_device", "negf_set_potential", "negf_set_potential_dev", "negf_solve",
+                 "negf_solve_ex", "negf_solve_dev", "negf_sync", "negf_lead_self_energy", "negf_set_profiling",
+                 "negf_kernel_times"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != NEGF_OK:
+        raise NegfError(status, load().negf_last_error().decode())
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def default_options() -> negf_options:
+    o = negf_options()
+    load().negf_default_options(C.byref(o))
+    return o
+
+
+@dataclass
+class SolveResult:
+    charge: np.ndarray
+    T: np.ndarray
+    current: float
+    gr_diag: Optional[np.ndarray] = None
+    al_diag: Optional[np.ndarray] = None
+    ar_diag: Optional[np.ndarray] = None
+    decim_iters: Optional[np.ndarray] = None
+
+
+class NegfDevice:
+    """One device handle (negf_create_device ... negf_destroy)."""
+
+    def __init__(self, dev: Device, precision: int = FP64, eta: float = 1e-6, decim_tol: float = 1e-12,
+                 decim_max_iter: int = 64, g_s: float = 2.0, workspace_bytes: int = 0):
+        lib = load()
+        self.N, self.b = dev.n_rings, dev.b
+        self._keep = []
+        hd = _c(dev.h_diag, np.complex128)
+        hu = _c(dev.h_up, np.complex128) if dev.n_rings > 1 else None
+        leads = [self._lead(dev.left), self._lead(dev.right)]
+        o = default_options()
+        o.precision, o.eta, o.decim_tol, o.decim_max_iter, o.g_s = precision, eta, decim_tol, decim_max_iter, g_s
+        o.workspace_bytes = workspace_bytes
+        h = C.c_void_p()
+        _check(lib.negf_create_device(C.byref(h), self.N, self.b, _ptr(hd), _ptr(hu), C.byref(leads[0]),
+                                      C.byref(leads[1]), C.byref(o)))
+        self.h = h
+        self.precision = precision
+        self._keep = []
+
+    def _lead(self, ld: Lead) -> negf_lead:
+        arrs = [_c(ld.h_diag, np.complex128), _c(ld.h_up, np.complex128), _c(ld.tau, np.complex128)]
+        self._keep.extend(arrs)
+        return negf_lead(ld.period, *(a.ctypes.data_as(C.c_void_p) for a in arrs))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().negf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---------------------------------------------------------------- host API
+    def set_potential(self, U: np.ndarray, U_left: float = 0.0, U_right: float = 0.0):
+        U = _c(U, np.float64)
+        if U.shape != (self.N * self.b,):
+            raise ValueError(f"U must have shape ({self.N * self.b},)")
+        _check(load().negf_set_potential(self.h, _ptr(U), float(U_left), float(U_right)))
+
+    def solve(self, bias: Bias, grid: EnergyGrid, details: bool = False) -> SolveResult:
+        zc, wc = _c(grid.z_c, np.complex128), _c(grid.w_c, np.complex128)
+        Er, wr = _c(grid.E_r, np.float64), _c(grid.w_r, np.float64)
+        nc, nr, nb = zc.shape[0], Er.shape[0], self.N * self.b
+        charge = np.zeros(nb)
+        T = np.zeros(nr)
+        cur = np.zeros(1)
+        out = negf_outputs(_ptr(charge), _ptr(T), _ptr(cur), None, None, None, None)
+        gr = al = ar = it = None
+        if details:
+            gr = np.zeros((nc, nb), np.complex128)
+            al = np.zeros((nr, nb))
+            ar = np.zeros((nr, nb))
+            it = np.zeros((nc + nr, 2), np.int32)
+            out.gr_diag, out.al_diag, out.ar_diag, out.decim_iters = _ptr(gr), _ptr(al), _ptr(ar), _ptr(it)
+        b = negf_bias(bias.mu_L, bias.mu_R, bias.kT_L, bias.kT_R)
+        _check(load().negf_solve_ex(self.h, C.byref(b), nc, _ptr(zc), _ptr(wc), nr, _ptr(Er), _ptr(wr),
+                                    C.byref(out)))
+        return SolveResult(charge, T, float(cur[0]), gr, al, ar, it)
+
+    def lead_self_energy(self, lead: int, z: np.ndarray):
+        z = _c(np.atleast_1d(z), np.complex128)
+        sig = np.zeros((z.shape[0], self.b, self.b), np.complex128)
+        it = np.zeros(z.shape[0], np.int32)
+        _check(load().negf_lead_self_energy(self.h, int(lead), z.shape[0], _ptr(z), _ptr(sig), _ptr(it)))
+        return sig, it
+
+    # -------------------------------------------------------------- device API
+    def solve_dev(self, bias: Bias, zc, wc, Er, wr, charge, T=None, current=None, stream=None):
+        """Enqueues a solve on `stream` (torch.cuda.Stream or raw handle); tensors are device tensors."""
+        b = negf_bias(bias.mu_L, bias.mu_R, bias.kT_L, bias.kT_R)
+        s = _stream_handle(stream)
+        nc = 0 if zc is None else int(zc.shape[0])
+        nr = 0 if Er is None else int(Er.shape[0])
+        _check(load().negf_solve_dev(self.h, C.byref(b), nc, _tp(zc), _tp(wc), nr, _tp(Er), _tp(wr), _tp(charge),
+                                     _tp(T), _tp(current), s))
+
+    def sync(self):
+        _check(load().negf_sync(self.h))
+
+    def set_profiling(self, on: bool):
+        _check(load().negf_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        n = C.c_int(16)
+        names = (C.c_char_p * 16)()
+        ms = (C.c_double * 16)()
+        calls = (C.c_int * 16)()
+        _check(load().negf_kernel_times(self.h, names, ms, calls, C.byref(n)))
+        return {names[k].decode(): (ms[k], calls[k]) for k in range(n.value)}
+
+    def device_bytes(self) -> int:
+        return int(load().negf_device_bytes(self.h))
+
+
+def _tp(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def solve_problem(p: Problem, precision: int = FP64, details: bool = False, **kw) -> SolveResult:
+    """Creates a handle for p.device, sets the potential and solves p's grid."""
+    with NegfDevice(p.device, precision=precision, eta=p.eta, decim_tol=p.decim_tol,
+                    decim_max_iter=p.decim_max_iter, g_s=p.g_s, **kw) as d:
+        d.set_potential(p.U, p.U_left, p.U_right)
+        return d.solve(p.bias, p.grid, details=details)

@@ -1,0 +1,223 @@
+"""HIP path vs the CPU oracle on identical seeded inputs (run on an MI355X).
+
+FP64 gate: 1e-10 relative on integrated per-atom charge (denominator max_i |charge_i|)
+and on the current; per-energy quantities are compared with a floor (the
+problem's own conditioning near resonances is ~1e-10 per energy).
+FP32-bulk gate: 1e-5 relative on charge and current.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import negf_oracle as O
+from paper_2407_14633_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b, floor=0.0):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), floor, 1e-300))
+
+
+def oracle_details(p):
+    return O.solve(p, details=True)
+
+
+# -------------------------------------------------------------- decimation ----
+def _lead_cases():
+    d8 = W.zigzag_cnt(8, 4)
+    d17 = W.zigzag_cnt(17, 4)
+    r1 = W.random_device(2, 3, seed=11, period=1, scale=0.7)
+    r2 = W.random_device(2, 4, seed=12, period=2, scale=0.7)
+    return [("cnt8", d8), ("cnt17", d17), ("rand_p1_b3", r1), ("rand_p2_b4", r2)]
+
+
+def _oracle_sensitivity(ld, Ul, z, ref, trials=2):
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for _ in range(trials):
+        jitter = lambda a: a * (1 + 2e-16 * rng.normal(size=a.shape))
+        l2 = W.Lead(ld.period, jitter(ld.h_diag), jitter(ld.h_up), ld.tau)
+        s2, _ = O.self_energy(l2, Ul, z)
+        worst = max(worst, rel(s2, ref))
+    return worst
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_decimation_matches_oracle(gpu_lib, case):
+    name, dev = _lead_cases()[case]
+    say("decimation", name)
+    z = np.array([0.3 + 1e-6j, -0.9 + 1e-6j, 1.7 + 1e-6j, -2.6 + 1e-3j, 0.8 + 0.4j, -5.0 + 2.0j, 0.05 + 1e-6j])
+    with gpu_lib.NegfDevice(dev) as d:
+        d.set_potential(np.zeros(dev.n_rings * dev.b), 0.07, -0.03)
+        for lead, ld, Ul in ((0, dev.left, 0.07), (1, dev.right, -0.03)):
+            sig, it = d.lead_self_energy(lead, z)
+            for k, zk in enumerate(z):
+                ref, itr = O.self_energy(ld, Ul, zk)
+                # the tolerance follows the node's own conditioning: how far the oracle
+                # moves when its inputs are perturbed at the rounding level
+                tol = max(1e-10, 20 * _oracle_sensitivity(ld, Ul, zk, ref))
+                assert rel(sig[k], ref) < tol, (name, lead, zk, rel(sig[k], ref), tol)
+                assert abs(int(it[k]) - itr) <= 1, (it[k], itr)
+
+
+def test_decimation_no_convergence_is_reported(gpu_lib):
+    dev = W.zigzag_cnt(8, 4)
+    with gpu_lib.NegfDevice(dev, decim_max_iter=2) as d:
+        with pytest.raises(gpu_lib.NegfError) as e:
+            d.lead_self_energy(1, np.array([0.5 + 1e-6j]))
+        assert e.value.status == gpu_lib.NEGF_ENOCONV
+
+
+# ------------------------------------------------------- tiny brute cases ----
+@pytest.mark.parametrize("N,b,period,seed", [(1, 3, 2, 1), (2, 1, 1, 2), (3, 2, 2, 3), (7, 5, 1, 4),
+                                             (5, 9, 2, 5), (4, 24, 1, 6), (6, 13, 2, 7)])
+def test_random_devices_match_oracle(gpu_lib, N, b, period, seed):
+    say("random device", N, b, period, seed)
+    dev = W.random_device(N, b, seed=seed, period=period, scale=0.6)
+    rng = np.random.default_rng(seed)
+    U = rng.uniform(-0.3, 0.3, N * b)
+    bias = W.Bias(0.15, -0.1, 0.05, 0.04)
+    grid = W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 6, 7)
+    p = W.Problem("rand", dev, U, 0.02, -0.04, bias, grid, eta=1e-4)
+    ref = oracle_details(p)
+    got = gpu_lib.solve_problem(p, details=True)
+    # energy-resolved arrays: 1e-9 (random complex blocks are less well conditioned);
+    # integrated charge and current: 1e-10
+    assert rel(got.gr_diag, ref["gr_diag"]) < 1e-9
+    assert rel(got.al_diag, ref["AL"]) < 1e-9
+    assert rel(got.ar_diag, ref["AR"]) < 1e-9
+    assert rel(got.T, ref["T"], floor=1e-12) < 1e-9
+    assert rel(got.charge, ref["charge"]) < 1e-10
+    assert abs(got.current - ref["current"]) <= 1e-10 * abs(ref["current"]) + 1e-25
+
+
+# --------------------------------------------------- (8,0), 64 rings, 256 E ----
+@pytest.fixture(scope="module")
+def small_ref():
+    p = W.small_problem()
+    return p, oracle_details(p)
+
+
+def test_small_problem_fp64(gpu_lib, small_ref):
+    p, ref = small_ref
+    say("small problem fp64")
+    got = gpu_lib.solve_problem(p, details=True)
+    e_q = rel(got.charge, ref["charge"])
+    e_T = rel(got.T, ref["T"], floor=1e-8 * np.max(ref["T"]))
+    say(f"  charge rel {e_q:.3e}  T rel {e_T:.3e}  current {got.current:.6e} vs {ref['current']:.6e}")
+    assert e_q < 1e-10
+    assert e_T < 1e-10
+    assert abs(got.current - ref["current"]) <= 1e-8 * abs(ref["current"]) + 1e-22
+    assert np.array_equal(got.decim_iters[:, 0] > 0, np.ones(256, bool))
+
+
+def test_small_problem_fp32_bulk(gpu_lib, small_ref):
+    p, ref = small_ref
+    got = gpu_lib.solve_problem(p, precision=gpu_lib.FP32_BULK)
+    e_q = rel(got.charge, ref["charge"])
+    say(f"  fp32-bulk small: charge rel {e_q:.3e}")
+    assert e_q < 1e-5
+
+
+def test_energy_chunking_is_bitwise_invariant(gpu_lib, small_ref):
+    p, _ = small_ref
+    a = gpu_lib.solve_problem(p)
+    per_energy = 2 * 64 * 8 * 8 * 16
+    b = gpu_lib.solve_problem(p, workspace_bytes=per_energy * 7)   # 7 energies per chunk, ragged tail
+    assert np.array_equal(a.charge, b.charge) and np.array_equal(a.T, b.T) and a.current == b.current
+
+
+def test_contour_only_and_real_only(gpu_lib):
+    dev = W.zigzag_cnt(9, 6)
+    U = W.potential_smooth_ring(6, 9, 0.2, seed=3)
+    bias = W.Bias(0.05, -0.05, 0.03, 0.03)
+    g = W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 20, 30)
+    for grid in (W.EnergyGrid(g.z_c, g.w_c, np.zeros(0), np.zeros(0)),
+                 W.EnergyGrid(np.zeros(0, complex), np.zeros(0, complex), g.E_r, g.w_r)):
+        p = W.Problem("part", dev, U, 0.0, 0.0, bias, grid)
+        ref = O.solve(p)
+        got = gpu_lib.solve_problem(p)
+        assert rel(got.charge, ref["charge"]) < 1e-10
+        assert abs(got.current - ref["current"]) <= 1e-10 * abs(ref["current"]) + 1e-25
+
+
+def test_neutral_metallic_tube_on_gpu(gpu_lib):
+    n, N = 9, 6
+    dev = W.zigzag_cnt(n, N)
+    U = np.zeros(N * n)
+    bias = W.Bias(0.0, 0.0, 0.05, 0.05)
+    grid = W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 48, 160)
+    got = gpu_lib.solve_problem(W.Problem("neutral", dev, U, 0.0, 0.0, bias, grid))
+    assert np.max(np.abs(got.charge - 1.0)) < 1e-7
+    assert got.current == 0.0
+
+
+def test_singular_block_is_reported(gpu_lib):
+    """A decoupled ring whose level sits exactly on a real node with eta = 0."""
+    b, N = 1, 3
+    one = np.ones((1, 1, 1), np.complex128)
+    ld = W.Lead(period=1, h_diag=0 * one, h_up=-1.0 * one, tau=-1.0 * one[0])
+    dev = W.Device(h_diag=np.zeros((N, 1, 1), np.complex128), h_up=np.zeros((N - 1, 1, 1), np.complex128),
+                   left=ld, right=ld)
+    U = np.array([0.0, 5.0, 0.0])
+    with gpu_lib.NegfDevice(dev, eta=0.0) as d:
+        d.set_potential(U)
+        grid = W.EnergyGrid(np.zeros(0, complex), np.zeros(0, complex), np.array([5.0]), np.array([0.1]))
+        with pytest.raises(gpu_lib.NegfError) as e:
+            d.solve(W.Bias(0.0, 0.0), grid)
+        assert e.value.status == gpu_lib.NEGF_ESINGULAR
+
+
+# ------------------------------------------ (17,0), 400 rings, 512 + 1536 E ----
+@pytest.fixture(scope="module")
+def device_sub():
+    p = W.device_problem(N=400)
+    sub = W.subsample_grid(p.grid, 12, 12, seed=77)
+    ps = W.with_grid(p, sub)
+    return p, ps, oracle_details(ps)
+
+
+def test_device_problem_sampled_fp64(gpu_lib, device_sub):
+    p, ps, ref = device_sub
+    say("device problem fp64 on 12+12 sampled nodes")
+    got = gpu_lib.solve_problem(ps, details=True)
+    e_q = rel(got.charge, ref["charge"])
+    e_c = abs(got.current - ref["current"]) / abs(ref["current"])
+    e_T = rel(got.T, ref["T"], floor=1e-8 * np.max(ref["T"]))
+    say(f"  charge rel {e_q:.3e}  current rel {e_c:.3e}  T rel {e_T:.3e}")
+    assert e_q < 1e-10 and e_c < 1e-10 and e_T < 1e-9
+    # energy-resolved diagonals with the per-energy floor
+    assert rel(got.gr_diag, ref["gr_diag"]) < 1e-8
+    for q in range(ps.grid.n_r):
+        fl = 1e-8 * max(np.max(ref["AL"][q]), np.max(ref["AR"][q]))
+        assert np.max(np.abs(got.al_diag[q] - ref["AL"][q])) <= max(fl, 1e-8 * np.max(ref["AL"][q]) + 1e-300)
+
+
+def test_device_problem_full_grid_T_samples(gpu_lib, device_sub):
+    """Full 512 + 1536 grid in the bench's launch shape; T checked at sampled nodes."""
+    p, _, _ = device_sub
+    got = gpu_lib.solve_problem(p)
+    assert np.all(np.isfinite(got.charge)) and got.charge.shape == (400 * 17,)
+    idx = np.random.default_rng(5).choice(p.grid.n_r, size=4, replace=False)
+    for q in idx:
+        _, _, Tq, _ = O.energy_point_real(p, p.grid.E_r[q])
+        assert abs(got.T[q] - Tq) <= 1e-9 * max(Tq, 1e-6), (q, got.T[q], Tq)
+    # physical sanity at any size: charge per atom within [0, 2]
+    assert np.all(got.charge > 0) and np.all(got.charge < 2)
+
+
+def test_device_problem_sampled_fp32_bulk(gpu_lib, device_sub):
+    p, ps, ref = device_sub
+    got = gpu_lib.solve_problem(ps, precision=gpu_lib.FP32_BULK)
+    e_q = rel(got.charge, ref["charge"])
+    e_c = abs(got.current - ref["current"]) / abs(ref["current"])
+    say(f"  fp32-bulk device: charge rel {e_q:.3e} current rel {e_c:.3e}")
+    assert e_q < 1e-5 and e_c < 1e-5
