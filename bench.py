@@ -92,11 +92,13 @@ def cpu_baseline(p: W.Problem, n_c: int = 8, n_r: int = 24, seed: int = 99) -> d
 
 
 def _oracle_point(args):
+    from threadpoolctl import threadpool_limits
     from oracle import negf_oracle as O
     p, kind, x = args
-    if kind == "c":
-        return O.energy_point_contour(p, x)
-    return O.energy_point_real(p, x)
+    with threadpool_limits(1):   # one BLAS thread per worker: `cores` counts worker processes
+        if kind == "c":
+            return O.energy_point_contour(p, x)
+        return O.energy_point_real(p, x)
 
 
 def run(p: W.Problem, precision: int, steps: int, warmup: int):
@@ -138,7 +140,39 @@ def run(p: W.Problem, precision: int, steps: int, warmup: int):
     return out
 
 
-def roofline(p, r, peak_tflops):
+def calibrate_copy(mib: int):
+    """A plain device-to-device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 8}), flush=True)
+
+
+def measured_traffic(kernel: str, b: int, precision: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH/WRITE summary,
+    or None when the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    if precision != "f64":
+        return None
+    src = os.path.join(ROOT, "paper_2407_14633_amd", "csrc", "negf_kernels.hpp")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    names = {"recur": f"negf::k_recur<double, {b}>", "cdiag": f"negf::k_cdiag<double, {b}>",
+             "column": f"negf::k_column<double, double, {b}>", "decimate": f"negf::k_decimate<{b}>"}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
+        for line in open(path):
+            if line.startswith("machine-readable: "):
+                d = json.loads(line[len("machine-readable: "):])
+                if d.get("source_hash") == h and names.get(kernel) in d.get("hbm_bytes", {}):
+                    return d["hbm_bytes"][names[kernel]]
+    return None
+
+
+def roofline(p, r, peak_tflops, precision="f64"):
     flops = algorithmic_flops(p, r["iters"])
     best = None
     for k, (ms, calls) in r["times"].items():
@@ -149,8 +183,8 @@ def roofline(p, r, peak_tflops):
     k, avg = best
     ach = flops[k] / (avg * 1e-3) / 1e12
     return {"kernel": k, "bound": "alu", "achieved": round(ach, 4), "peak": peak_tflops, "unit": "TFLOP/s",
-            "frac": round(ach / peak_tflops, 5), "traffic": None, "avg_ms": round(avg, 4),
-            "flops_per_launch": flops[k]}
+            "frac": round(ach / peak_tflops, 5), "traffic": measured_traffic(k, p.device.b, precision),
+            "avg_ms": round(avg, 4), "flops_per_launch": flops[k]}
 
 
 def main():
@@ -161,7 +195,12 @@ def main():
     ap.add_argument("--workload", default="device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     a = ap.parse_args()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the energy-point solve on a single MI355X "
               "(energy nodes would shard across GPUs with one all-reduce of the charge; not built here).",
@@ -182,7 +221,7 @@ def main():
     if not a.no_fp32:
         r32 = run(p, negf.FP32_BULK, a.steps, a.warmup)
         log("fp32-bulk ms/step", r32["ms_per_step"], "kernels", r32["times"])
-        rf32 = roofline(p, r32, FP32_PEAK_TFLOPS)
+        rf32 = roofline(p, r32, FP32_PEAK_TFLOPS, "f32")
         err = float(np.max(np.abs(r32["charge"] - r64["charge"])) / np.max(np.abs(r64["charge"])))
         fp32 = {"value": n_e / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
                 "roofline": rf32, "charge_rel_diff_vs_fp64": err,

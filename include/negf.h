@@ -70,9 +70,9 @@ typedef struct {
 } negf_lead;
 
 typedef struct {
-    int precision;            /* NEGF_FP64, or NEGF_FP32_BULK: recursions and block
-                                 products in complex FP32; decimation and the energy
-                                 sums stay FP64                                      */
+    int precision;            /* NEGF_FP64, or NEGF_FP32_BULK: recursions, inversions
+                                 and block products in complex FP32 with FP32
+                                 accumulation; decimation and the energy sums FP64  */
     double eta;               /* i*eta added to real-axis nodes (device and leads)   */
     double decim_tol;         /* stop when max |alpha_ij|, |beta_ij| < decim_tol (eV) */
     int decim_max_iter;       /* NEGF_ENOCONV beyond this many doubling steps        */

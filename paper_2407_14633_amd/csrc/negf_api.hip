@@ -153,7 +153,9 @@ void dfree(negf_device* d, void* p, size_t bytes) {
         if (s_ != NEGF_OK) return s_;   \
     } while (0)
 
+// element sizes per precision: recursion store / contour diagonals (complex), A diagonals (real)
 size_t cplx_bytes(const negf_device* d) { return d->opt.precision == NEGF_FP32_BULK ? 8 : 16; }
+size_t adiag_bytes(const negf_device* d) { return d->opt.precision == NEGF_FP32_BULK ? 4 : 8; }
 
 size_t store_bytes_per_energy(const negf_device* d) {
     return (size_t)d->N * d->b * d->b * cplx_bytes(d);
@@ -162,7 +164,7 @@ size_t store_bytes_per_energy(const negf_device* d) {
 negf_status ensure_energy_ws(negf_device* d, int ne) {
     if (ne <= d->cap_e) return NEGF_OK;
     const size_t b2 = (size_t)d->b * d->b, Nb = (size_t)d->N * d->b;
-    const size_t cb = cplx_bytes(d), rb = cb / 2;
+    const size_t cb = cplx_bytes(d), rb = adiag_bytes(d);
     size_t old = d->cap_e;
     dfree(d, d->d_z, old * 16);
     dfree(d, d->d_sigma, old * 2 * b2 * 16);
@@ -329,12 +331,8 @@ negf_status run_solve(negf_device* d, const negf_bias* bias, int n_c, const cx<d
     TRY(ensure_energy_ws(d, ne));
     const int chunk = chunk_energies(d, ne);
     TRY(ensure_store(d, chunk));
-    if (!d->d_flags) {
-        TRY(dalloc(d, &d->d_flags, 2 * sizeof(int)));
-        HIPCHK(hipHostMalloc((void**)&d->h_flags, 2 * sizeof(int), hipHostMallocDefault));
-    }
     const int N = d->N, b = d->b, G = d->L->groups;
-    const bool f32 = d->opt.precision == NEGF_FP32_BULK;
+    const bool f32 = d->opt.precision == NEGF_FP32_BULK;       // everything but a1/a6 in FP32
     hipEvent_t ev;
 
     ev_begin(d, KT_REDUCE, s, &ev);
@@ -429,12 +427,11 @@ negf_status run_solve(negf_device* d, const negf_bias* bias, int n_c, const cx<d
     ev_begin(d, KT_REDUCE, s, &ev);
     hipLaunchKernelGGL(negf::k_coef, dim3((ne + 255) / 256), dim3(256), 0, s, R);
     if (!d->d_part) TRY(dalloc(d, &d->d_part, (size_t)negf::RED_SEGS * R.Nb * 8));
+    const dim3 rgrid((R.Nb + 255) / 256, negf::RED_SEGS);
     if (f32)
-        hipLaunchKernelGGL(negf::k_reduce_part<float>, dim3((R.Nb + 255) / 256, negf::RED_SEGS), dim3(256), 0, s, R,
-                           d->d_part);
+        hipLaunchKernelGGL((negf::k_reduce_part<float, float>), rgrid, dim3(256), 0, s, R, d->d_part);
     else
-        hipLaunchKernelGGL(negf::k_reduce_part<double>, dim3((R.Nb + 255) / 256, negf::RED_SEGS), dim3(256), 0, s, R,
-                           d->d_part);
+        hipLaunchKernelGGL((negf::k_reduce_part<double, double>), rgrid, dim3(256), 0, s, R, d->d_part);
     hipLaunchKernelGGL(negf::k_reduce_final, dim3((R.Nb + 255) / 256), dim3(256), 0, s, R, d->d_part);
     if (n_r > 0)
         hipLaunchKernelGGL(negf::k_current, dim3(1), dim3(64), 0, s, R);
@@ -614,6 +611,11 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
     }
     if (hipStreamCreateWithFlags(&d->own_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(NEGF_EHIP, "stream creation failed"));
+    if ((s = dalloc(d, &d->d_flags, 2 * sizeof(int))) != NEGF_OK) return bail(s);
+    if (hipHostMalloc((void**)&d->h_flags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(NEGF_ENOMEM, "pinned flag buffer"));
+    d->h_flags[0] = 0;
+    d->h_flags[1] = 0;
     d->last_stream = d->own_stream;
     *out = d;
     return NEGF_OK;
@@ -701,6 +703,7 @@ negf_status negf_solve_ex(negf_device* d, const negf_bias* bias, int n_c, const 
     if (out->current) HIPCHK(hipMemcpy(out->current, d->d_out_cur, 8, hipMemcpyDeviceToHost));
     if (out->T && n_r) HIPCHK(hipMemcpy(out->T, d->d_T, (size_t)n_r * 8, hipMemcpyDeviceToHost));
     const bool f32 = d->opt.precision == NEGF_FP32_BULK;
+    const bool ad32 = f32;
     if (out->gr_diag && n_c) {
         if (f32) {
             std::vector<float> tmp((size_t)n_c * Nb * 2);
@@ -712,7 +715,7 @@ negf_status negf_solve_ex(negf_device* d, const negf_bias* bias, int n_c, const 
     }
     if ((out->al_diag || out->ar_diag) && n_r) {
         std::vector<double> ad((size_t)n_r * 2 * Nb);
-        if (f32) {
+        if (ad32) {
             std::vector<float> tmp(ad.size());
             HIPCHK(hipMemcpy(tmp.data(), d->d_ad, tmp.size() * 4, hipMemcpyDeviceToHost));
             for (size_t i = 0; i < ad.size(); ++i) ad[i] = tmp[i];
@@ -747,10 +750,6 @@ negf_status negf_lead_self_energy(negf_device* d, int lead, int n, const negf_c6
         if (!std::isfinite(z[i].re) || !std::isfinite(z[i].im)) return fail(NEGF_EINVAL, "z[%d] not finite", i);
     HIPCHK(hipSetDevice(d->dev_id));
     TRY(ensure_energy_ws(d, n));
-    if (!d->d_flags) {
-        TRY(dalloc(d, &d->d_flags, 2 * sizeof(int)));
-        HIPCHK(hipHostMalloc((void**)&d->h_flags, 2 * sizeof(int), hipHostMallocDefault));
-    }
     hipStream_t s = d->own_stream;
     const int b = d->b, G = d->L->groups;
     HIPCHK(hipMemcpyAsync(d->d_z, z, (size_t)n * 16, hipMemcpyHostToDevice, s));

@@ -458,7 +458,7 @@ __global__ __launch_bounds__(64, 2) void k_cdiag(RgfArgs A, int nc_chunk) {
 // Each ring's diag(W Gamma W^H) is written; the right chain ends with
 // T_LR = Tr[Gamma_L W_0 Gamma_R W_0^H] (Eq. 5).
 // Grid: [2 * ceil(nr_chunk / G)], first half left lead.
-template <typename T, int B>
+template <typename T, typename TS, int B>
 __global__ __launch_bounds__(64, 2) void k_column(RgfArgs A, int er0, int nr_chunk) {
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
@@ -490,14 +490,14 @@ __global__ __launch_bounds__(64, 2) void k_column(RgfArgs A, int er0, int nr_chu
             Gm[r * B + j] = cx<T>{T(-(a.im + b.im)), T(a.re - b.re)};
         }
     }
-    const cx<T>* store = reinterpret_cast<const cx<T>*>(lead ? A.store_f : A.store_b) + (size_t)(act ? el : 0) * N * B * B;
+    const cx<TS>* store = reinterpret_cast<const cx<TS>*>(lead ? A.store_f : A.store_b) + (size_t)(act ? el : 0) * N * B * B;
     T wr[B], wi[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) { wr[j] = T(0); wi[j] = T(0); }
     if (act) {
-        const cx<T>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
+        const cx<TS>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
 #pragma unroll
-        for (int j = 0; j < B; ++j) { const cx<T> v = w0[j]; wr[j] = v.re; wi[j] = v.im; }
+        for (int j = 0; j < B; ++j) { const cx<TS> v = w0[j]; wr[j] = T(v.re); wi[j] = T(v.im); }
     }
     stage_row<T, B>(wr, wi, S, r, act);
     wave_sync();
@@ -511,9 +511,9 @@ __global__ __launch_bounds__(64, 2) void k_column(RgfArgs A, int er0, int nr_chu
 #pragma unroll
         for (int j = 0; j < B; ++j) { pr[j] = T(0); pi[j] = T(0); }
         if (act && s < N - 1) {
-            const cx<T>* p = store + ((size_t)n * B + r) * B;
+            const cx<TS>* p = store + ((size_t)n * B + r) * B;
 #pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<T> v = p[j]; pr[j] = -v.re; pi[j] = -v.im; }
+            for (int j = 0; j < B; ++j) { const cx<TS> v = p[j]; pr[j] = -T(v.re); pi[j] = -T(v.im); }
         }
         // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j])
         row_mul<T, B>(wr, wi, Gm, vr, vi);

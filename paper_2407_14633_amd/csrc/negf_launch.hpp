@@ -32,13 +32,13 @@ struct LaunchImpl {
     static void cdiag(const RgfArgs& a, int nc, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_cdiag<T, B>), dim3(grid), dim3(64), 0, s, a, nc);
     }
-    template <typename T>
+    template <typename T, typename S>
     static void column(const RgfArgs& a, int er0, int nr, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_column<T, B>), dim3(grid), dim3(64), 0, s, a, er0, nr);
+        hipLaunchKernelGGL((k_column<T, S, B>), dim3(grid), dim3(64), 0, s, a, er0, nr);
     }
     static const Launchers* table() {
         static const Launchers t = {B, 64 / B, &decimate, &recur<double>, &recur<float>,
-                                    &cdiag<double>, &cdiag<float>, &column<double>, &column<float>};
+                                    &cdiag<double>, &cdiag<float>, &column<double, double>, &column<float, float>};
         return &t;
     }
 };

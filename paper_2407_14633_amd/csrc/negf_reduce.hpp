@@ -67,7 +67,7 @@ __global__ void k_coef(RedArgs R) {
 // segments are added in order.  The result depends only on the node list.
 constexpr int RED_SEGS = 32;
 
-template <typename T>
+template <typename TG, typename TA>
 __global__ void k_reduce_part(RedArgs R, double* part) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int seg = blockIdx.y;
@@ -75,11 +75,11 @@ __global__ void k_reduce_part(RedArgs R, double* part) {
     const int ne = R.n_c + R.n_r;
     const int e_lo = (int)(((long long)ne * seg) / RED_SEGS), e_hi = (int)(((long long)ne * (seg + 1)) / RED_SEGS);
     double acc_c = 0.0, acc_r = 0.0;
-    const cx<T>* gr = reinterpret_cast<const cx<T>*>(R.gr_diag);
-    const T* ad = reinterpret_cast<const T*>(R.a_diag);
+    const cx<TG>* gr = reinterpret_cast<const cx<TG>*>(R.gr_diag);
+    const TA* ad = reinterpret_cast<const TA*>(R.a_diag);
     for (int e = e_lo; e < e_hi; ++e) {
         if (e < R.n_c) {
-            const cx<T> gv = gr[(size_t)e * R.Nb + i];
+            const cx<TG> gv = gr[(size_t)e * R.Nb + i];
             const cx<double> w = R.coef_c[e];
             acc_c += w.re * (double)gv.im + w.im * (double)gv.re;    // Im(w G)
         } else {
