@@ -162,11 +162,53 @@ negf_status negf_lead_self_energy(negf_device *d, int lead, int n, const negf_c6
 negf_status negf_set_profiling(negf_device *d, int enable);
 negf_status negf_kernel_times(negf_device *d, const char **names, double *ms, int *calls, int *count);
 
-/* Device memory held by the handle (bytes). */
+/* Device memory held by the handle and its private workspace (bytes). */
 size_t negf_device_bytes(const negf_device *d);
 
 void negf_destroy(negf_device *d);
 const char *negf_last_error(void);
+
+/* ------------------------------------------------------------ batches ----
+ * Many devices' energy nodes in the same launches (one set of persistent
+ * kernels per ring size and precision, longest chains first).  A job's
+ * results are bit-identical to its solo solve: no arithmetic depends on which
+ * other chains share a launch.  Jobs may use different ring sizes, lengths,
+ * node counts, biases and precisions; all devices must live on the workspace's
+ * HIP device.  The same negf_device may not appear twice in one batch only if
+ * the jobs need different potentials (the potential belongs to the device).
+ */
+typedef struct negf_workspace negf_workspace;
+
+typedef struct {
+    negf_device *dev;          /* device (Hamiltonian, leads, potential, options)    */
+    negf_bias bias;
+    int n_c; const negf_c64 *z_c, *w_c;   /* contour nodes and weights                */
+    int n_r; const double *E_r, *w_r;     /* real-axis nodes and weights              */
+    double *charge;            /* [N*b] output                                        */
+    double *T;                 /* [n_r] output or NULL                                */
+    double *current;           /* [1]   output or NULL                                */
+} negf_job;
+
+/* Workspace for batches: recursion stores, per-node arrays and the job/span
+ * tables, grown on demand and kept between solves.  store_bytes caps each of the
+ * two recursion stores (0 = 8 GiB); node ranges that do not fit run in several
+ * chunks.  Solves on one workspace are serialised on the device (a solve on
+ * another stream waits for the previous one); the tables are uploaded only when
+ * the job list changes.  Not thread-safe. */
+negf_status negf_workspace_create(negf_workspace **out, size_t store_bytes);
+void negf_workspace_destroy(negf_workspace *w);
+size_t negf_workspace_bytes(const negf_workspace *w);
+negf_status negf_workspace_set_profiling(negf_workspace *w, int enable);
+negf_status negf_workspace_kernel_times(negf_workspace *w, const char **names, double *ms, int *calls, int *count);
+/* Persistent workgroups launched per (resident workgroups x compute units), 1..64. */
+negf_status negf_workspace_set_grid_scale(negf_workspace *w, int scale);
+
+/* Host pointers, synchronous.  Returns the first failing job's status. */
+negf_status negf_batch_solve(negf_workspace *w, int n_jobs, const negf_job *jobs);
+/* Device pointers, asynchronous on hip_stream; statuses via negf_batch_sync
+ * (failed_job, if not NULL, receives the index of a failed job or -1). */
+negf_status negf_batch_solve_dev(negf_workspace *w, int n_jobs, const negf_job *jobs, void *hip_stream);
+negf_status negf_batch_sync(negf_workspace *w, int *failed_job);
 
 #ifdef __cplusplus
 }

@@ -1,5 +1,5 @@
 // C ABI of the energy-point Green's-function engine: argument checks, HBM
-// layout, energy chunking and the launch sequence of one solve.
+// layout, job/span scheduling, energy chunking and the launch sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -30,10 +31,16 @@ negf_status fail(negf_status s, const char* fmt, ...) {
     return s;
 }
 
-#define HIPCHK(expr)                                                                    \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess) return fail(NEGF_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(NEGF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+#define TRY(expr)                       \
+    do {                                \
+        negf_status s_ = (expr);        \
+        if (s_ != NEGF_OK) return s_;   \
     } while (0)
 
 const negf::Launchers* launchers_for(int b) {
@@ -58,7 +65,7 @@ const char* const kKernelNames[KT_COUNT] = {"decimate", "recur", "cdiag", "colum
 
 struct LeadDev {
     int period = 1;
-    std::vector<negf_c64> h_diag;   // host copy, potential added at set_potential
+    std::vector<negf_c64> h_diag;   // host copy, lead potential added on upload
     cx<double>* D = nullptr;        // [P][b][b] incl. lead potential
     cx<double>* V = nullptr;        // h_up[0]
     cx<double>* VH = nullptr;       // h_up[0]^H
@@ -66,18 +73,46 @@ struct LeadDev {
     cx<double>* tau = nullptr;
 };
 
+// A growable device buffer (contents are not preserved when it grows).
+struct DBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
 }  // namespace
+
+struct negf_workspace {
+    int dev_id = 0;
+    size_t store_cap = 0;     // bytes per recursion store direction; 0 = default
+    int cus = 0;
+    DBuf tables, counters, z, sigma, iters, status, coef_c, coef_r, T, gr, ad, part, store_f, store_b, scratch,
+        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur;
+    std::vector<char> last_tables;   // host image of `tables` (re-uploaded only when it changes)
+    hipEvent_t done = nullptr;       // recorded after each enqueued solve
+    int* h_flags = nullptr;   // pinned [2 * cap_flags]
+    int cap_flags = 0;
+    int last_n_jobs = 0;
+    std::vector<int> last_max_iter;
+    hipStream_t own_stream = nullptr;
+    // profiling
+    bool prof = false;
+    struct Ev { int kind; hipEvent_t a, b; };
+    std::vector<Ev> pending;
+    double ms[KT_COUNT] = {0};
+    int calls[KT_COUNT] = {0};
+    size_t bytes = 0;
+    int grid_scale = 1;       // persistent workgroups per (resident workgroups x CU)
+};
 
 struct negf_device {
     int dev_id = 0;
     int N = 0, b = 0;
     negf_options opt{};
     const negf::Launchers* L = nullptr;
-    int K = 1;
+    int K = 1, n_uniq = 1;
     bool hdiag_zero = true;
     double* d_U = nullptr;
     cx<double>* d_hdiag = nullptr;
-    int n_uniq = 1;
     int* d_ell_map = nullptr;
     int* d_cidx = nullptr;
     cx<double>* d_cval = nullptr;
@@ -85,149 +120,52 @@ struct negf_device {
     cx<double>* d_rval = nullptr;
     LeadDev lead[2];
     double U_lead[2] = {0.0, 0.0};
-
-    // per-energy workspace (capacity in energies)
-    int cap_e = 0;
-    cx<double>* d_z = nullptr;
-    cx<double>* d_sigma = nullptr;
-    int* d_iters = nullptr;
-    int* d_status = nullptr;
-    cx<double>* d_dscratch = nullptr;
-    cx<double>* d_coef_c = nullptr;
-    double* d_coef_r = nullptr;
-    void* d_gr = nullptr;
-    void* d_ad = nullptr;
-    double* d_T = nullptr;
-    double* d_part = nullptr;     // [RED_SEGS][N*b] reduction partials
-    // recursion store (capacity in energies)
-    int cap_store = 0;
-    void* d_store_f = nullptr;
-    void* d_store_b = nullptr;
-    // host-pointer staging
-    int cap_io = 0;
-    cx<double>* d_in_zc = nullptr;
-    cx<double>* d_in_wc = nullptr;
-    double* d_in_Er = nullptr;
-    double* d_in_wr = nullptr;
-    double* d_out_charge = nullptr;
-    double* d_out_cur = nullptr;
-    int* d_flags = nullptr;     // [0] flags, [1] first bad energy
-    int* h_flags = nullptr;     // pinned
-    hipStream_t own_stream = nullptr;
-    hipStream_t last_stream = nullptr;
-    int last_ne = 0;
-
-    bool prof = false;
-    struct Ev { int kind; hipEvent_t a, b; };
-    std::vector<Ev> pending;
-    double ms[KT_COUNT] = {0};
-    int calls[KT_COUNT] = {0};
-
+    negf_workspace* ws = nullptr;   // private workspace of the single-device calls
     size_t bytes = 0;
-    std::vector<void*> allocs_fixed;
 };
 
 namespace {
 
-template <typename P>
-negf_status dalloc(negf_device* d, P** p, size_t bytes) {
+negf_status dalloc_raw(size_t* counter, void** p, size_t bytes) {
     if (bytes == 0) bytes = 16;
     void* q = nullptr;
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) return fail(NEGF_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    *p = q;
+    *counter += bytes;
+    return NEGF_OK;
+}
+
+template <typename P>
+negf_status dalloc(negf_device* d, P** p, size_t bytes) {
+    void* q = nullptr;
+    TRY(dalloc_raw(&d->bytes, &q, bytes));
     *p = static_cast<P*>(q);
-    d->bytes += bytes;
     return NEGF_OK;
 }
 
-void dfree(negf_device* d, void* p, size_t bytes) {
-    if (p) {
-        (void)hipFree(p);
-        d->bytes -= std::min(d->bytes, bytes);
+// waits until the last enqueued solve of w has finished on the device
+negf_status wait_prev(negf_workspace* w) {
+    HIPCHK(hipEventSynchronize(w->done));
+    return NEGF_OK;
+}
+
+negf_status grow(negf_workspace* w, DBuf& buf, size_t bytes) {
+    if (bytes <= buf.cap && buf.p) return NEGF_OK;
+    if (buf.p) {
+        TRY(wait_prev(w));   // the previous solve may still use it
+        (void)hipFree(buf.p);
+        w->bytes -= std::min(w->bytes, buf.cap);
+        buf.p = nullptr;
+        buf.cap = 0;
     }
-}
-
-#define TRY(expr)                       \
-    do {                                \
-        negf_status s_ = (expr);        \
-        if (s_ != NEGF_OK) return s_;   \
-    } while (0)
-
-// element sizes per precision: recursion store / contour diagonals (complex), A diagonals (real)
-size_t cplx_bytes(const negf_device* d) { return d->opt.precision == NEGF_FP32_BULK ? 8 : 16; }
-size_t adiag_bytes(const negf_device* d) { return d->opt.precision == NEGF_FP32_BULK ? 4 : 8; }
-
-size_t store_bytes_per_energy(const negf_device* d) {
-    return (size_t)d->N * d->b * d->b * cplx_bytes(d);
-}
-
-negf_status ensure_energy_ws(negf_device* d, int ne) {
-    if (ne <= d->cap_e) return NEGF_OK;
-    const size_t b2 = (size_t)d->b * d->b, Nb = (size_t)d->N * d->b;
-    const size_t cb = cplx_bytes(d), rb = adiag_bytes(d);
-    size_t old = d->cap_e;
-    dfree(d, d->d_z, old * 16);
-    dfree(d, d->d_sigma, old * 2 * b2 * 16);
-    dfree(d, d->d_iters, old * 2 * 4);
-    dfree(d, d->d_status, old * 4);
-    dfree(d, d->d_dscratch, old * 2 * 6 * b2 * 16);
-    dfree(d, d->d_coef_c, old * 16);
-    dfree(d, d->d_coef_r, old * 3 * 8);
-    dfree(d, d->d_gr, old * Nb * cb);
-    dfree(d, d->d_ad, old * 2 * Nb * rb);
-    dfree(d, d->d_T, old * 8);
-    d->cap_e = 0;
-    const size_t n = (size_t)ne;
-    TRY(dalloc(d, &d->d_z, n * 16));
-    TRY(dalloc(d, &d->d_sigma, n * 2 * b2 * 16));
-    TRY(dalloc(d, &d->d_iters, n * 2 * 4));
-    TRY(dalloc(d, &d->d_status, n * 4));
-    TRY(dalloc(d, &d->d_dscratch, n * 2 * 6 * b2 * 16));
-    TRY(dalloc(d, &d->d_coef_c, n * 16));
-    TRY(dalloc(d, &d->d_coef_r, n * 3 * 8));
-    TRY(dalloc(d, &d->d_gr, n * Nb * cb));
-    TRY(dalloc(d, &d->d_ad, n * 2 * Nb * rb));
-    TRY(dalloc(d, &d->d_T, n * 8));
-    d->cap_e = ne;
+    const size_t want = std::max<size_t>(bytes, 256);
+    TRY(dalloc_raw(&w->bytes, &buf.p, want));
+    buf.cap = want;
     return NEGF_OK;
 }
 
-negf_status ensure_store(negf_device* d, int ne_chunk) {
-    if (ne_chunk <= d->cap_store) return NEGF_OK;
-    const size_t per = store_bytes_per_energy(d);
-    dfree(d, d->d_store_f, (size_t)d->cap_store * per);
-    dfree(d, d->d_store_b, (size_t)d->cap_store * per);
-    d->cap_store = 0;
-    TRY(dalloc(d, &d->d_store_f, (size_t)ne_chunk * per));
-    TRY(dalloc(d, &d->d_store_b, (size_t)ne_chunk * per));
-    d->cap_store = ne_chunk;
-    return NEGF_OK;
-}
-
-negf_status ensure_io(negf_device* d, int n_c, int n_r) {
-    const int need = std::max(n_c, n_r);
-    if (need > d->cap_io) {
-        const size_t old = d->cap_io;
-        dfree(d, d->d_in_zc, old * 16);
-        dfree(d, d->d_in_wc, old * 16);
-        dfree(d, d->d_in_Er, old * 8);
-        dfree(d, d->d_in_wr, old * 8);
-        d->cap_io = 0;
-        TRY(dalloc(d, &d->d_in_zc, (size_t)need * 16));
-        TRY(dalloc(d, &d->d_in_wc, (size_t)need * 16));
-        TRY(dalloc(d, &d->d_in_Er, (size_t)need * 8));
-        TRY(dalloc(d, &d->d_in_wr, (size_t)need * 8));
-        d->cap_io = need;
-    }
-    return NEGF_OK;
-}
-
-int chunk_energies(const negf_device* d, int ne) {
-    size_t cap = d->opt.workspace_bytes ? d->opt.workspace_bytes : ((size_t)16 << 30);
-    const size_t per = 2 * store_bytes_per_energy(d);
-    size_t c = std::max<size_t>(1, cap / per);
-    return (int)std::min<size_t>(c, (size_t)ne);
-}
+constexpr size_t kDefaultStoreCap = (size_t)8 << 30;
 
 negf_status upload_lead_D(negf_device* d, int l) {
     LeadDev& ld = d->lead[l];
@@ -250,210 +188,587 @@ negf_status check_lead(const negf_lead* ld, int b, const char* which) {
     return NEGF_OK;
 }
 
-negf_status check_solve_args(negf_device* d, const negf_bias* bias, int n_c, const void* z_c, const void* w_c,
-                             int n_r, const void* E_r, const void* w_r, const void* charge) {
-    if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
-    if (!bias) return fail(NEGF_EINVAL, "bias is NULL");
-    if (!(bias->kT_L > 0) || !(bias->kT_R > 0) || !std::isfinite(bias->mu_L) || !std::isfinite(bias->mu_R) ||
-        !std::isfinite(bias->kT_L) || !std::isfinite(bias->kT_R))
-        return fail(NEGF_EINVAL, "bias needs finite mu and kT > 0");
-    if (n_c < 0 || n_r < 0) return fail(NEGF_EINVAL, "negative node count (n_c=%d, n_r=%d)", n_c, n_r);
-    if (n_c + n_r < 1) return fail(NEGF_EINVAL, "no energy nodes");
-    if ((long long)n_c + n_r > (1LL << 26)) return fail(NEGF_EINVAL, "too many energy nodes");
-    if (n_c > 0 && (!z_c || !w_c)) return fail(NEGF_EINVAL, "contour nodes/weights are NULL");
-    if (n_r > 0 && (!E_r || !w_r)) return fail(NEGF_EINVAL, "real-axis nodes/weights are NULL");
-    if (!charge) return fail(NEGF_EINVAL, "charge output is NULL");
+negf_status check_job(const negf_job& j, int idx, bool host) {
+    if (!j.dev) return fail(NEGF_EINVAL, "job %d: device handle is NULL", idx);
+    const negf_bias& b = j.bias;
+    if (!(b.kT_L > 0) || !(b.kT_R > 0) || !std::isfinite(b.mu_L) || !std::isfinite(b.mu_R) ||
+        !std::isfinite(b.kT_L) || !std::isfinite(b.kT_R))
+        return fail(NEGF_EINVAL, "job %d: bias needs finite mu and kT > 0", idx);
+    if (j.n_c < 0 || j.n_r < 0)
+        return fail(NEGF_EINVAL, "job %d: negative node count (n_c=%d, n_r=%d)", idx, j.n_c, j.n_r);
+    if (j.n_c + j.n_r < 1) return fail(NEGF_EINVAL, "job %d: no energy nodes", idx);
+    if ((long long)j.n_c + j.n_r > (1LL << 26)) return fail(NEGF_EINVAL, "job %d: too many energy nodes", idx);
+    if (j.n_c > 0 && (!j.z_c || !j.w_c)) return fail(NEGF_EINVAL, "job %d: contour nodes/weights are NULL", idx);
+    if (j.n_r > 0 && (!j.E_r || !j.w_r)) return fail(NEGF_EINVAL, "job %d: real-axis nodes/weights are NULL", idx);
+    if (!j.charge) return fail(NEGF_EINVAL, "job %d: charge output is NULL", idx);
+    if (host) {
+        for (int i = 0; i < j.n_c; ++i)
+            if (!std::isfinite(j.z_c[i].re) || !std::isfinite(j.z_c[i].im) || !std::isfinite(j.w_c[i].re) ||
+                !std::isfinite(j.w_c[i].im))
+                return fail(NEGF_EINVAL, "job %d: contour node %d is not finite", idx, i);
+        for (int i = 0; i < j.n_r; ++i)
+            if (!std::isfinite(j.E_r[i]) || !std::isfinite(j.w_r[i]))
+                return fail(NEGF_EINVAL, "job %d: real node %d is not finite", idx, i);
+    }
     return NEGF_OK;
 }
 
-void ev_begin(negf_device* d, int kind, hipStream_t s, hipEvent_t* a) {
+void ev_begin(negf_workspace* w, hipStream_t s, hipEvent_t* a) {
     *a = nullptr;
-    if (!d->prof) return;
+    if (!w->prof) return;
     (void)hipEventCreate(a);
     (void)hipEventRecord(*a, s);
-    (void)kind;
 }
-void ev_end(negf_device* d, int kind, hipStream_t s, hipEvent_t a) {
-    if (!d->prof || !a) return;
+void ev_end(negf_workspace* w, int kind, hipStream_t s, hipEvent_t a) {
+    if (!w->prof || !a) return;
     hipEvent_t b;
     (void)hipEventCreate(&b);
     (void)hipEventRecord(b, s);
-    d->pending.push_back({kind, a, b});
+    w->pending.push_back({kind, a, b});
 }
-void ev_collect(negf_device* d) {
-    for (auto& e : d->pending) {
+void ev_collect(negf_workspace* w) {
+    for (auto& e : w->pending) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
-            d->ms[e.kind] += t;
-            d->calls[e.kind] += 1;
+            w->ms[e.kind] += t;
+            w->calls[e.kind] += 1;
         }
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
-    d->pending.clear();
+    w->pending.clear();
 }
 
-__global__ void k_fill_int(int* p, int n, int v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+// persistent grid: resident workgroups x CUs x grid_scale, capped by the units
+int persistent_grid(negf_workspace* w, const void* func, size_t dyn, long long units) {
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, 64, dyn) != hipSuccess || per_cu < 1) per_cu = 1;
+    const long long g = (long long)per_cu * std::max(1, w->cus) * std::max(1, w->grid_scale);
+    return (int)std::max<long long>(1, std::min<long long>(g, units));
 }
-__global__ void k_zero_double(double* p) { *p = 0.0; }
 
-negf::DecArgs dec_args(negf_device* d, int n, int lead_only) {
-    negf::DecArgs a{};
-    a.b = d->b;
-    a.n = n;
-    a.maxit = d->opt.decim_max_iter;
-    a.tol = d->opt.decim_tol;
-    a.lead_only = lead_only;
-    a.z = d->d_z;
-    for (int l = 0; l < 2; ++l) {
-        a.period[l] = d->lead[l].period;
-        a.D[l] = d->lead[l].D;
-        a.V[l] = d->lead[l].V;
-        a.VH[l] = d->lead[l].VH;
-        a.W[l] = d->lead[l].W;
-        a.tau[l] = d->lead[l].tau;
+struct JobPlan {
+    negf_device* d;
+    int ne;
+    size_t o_node, o_sigma, o_gr, o_ad, o_part;   // element offsets in the workspace arrays
+};
+
+// Enqueues one solve of all jobs on stream s.  All job pointers are device pointers.
+negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStream_t s,
+                    bool decimation_only = false) {
+    HIPCHK(hipSetDevice(w->dev_id));
+    // a solve on another stream starts after the previous one (shared arrays)
+    HIPCHK(hipStreamWaitEvent(s, w->done, 0));
+    // ---- per-job array layout
+    std::vector<JobPlan> plan(n_jobs);
+    size_t nodes = 0, sig = 0, gr64 = 0, gr32 = 0, ad64 = 0, ad32 = 0, part = 0;
+    int max_ne = 0, max_nb = 0;
+    w->last_max_iter.assign(n_jobs, 0);
+    for (int i = 0; i < n_jobs; ++i) {
+        negf_device* d = jobs[i].dev;
+        const int ne = jobs[i].n_c + jobs[i].n_r;
+        const size_t Nb = (size_t)d->N * d->b, b2 = (size_t)d->b * d->b;
+        JobPlan& p = plan[i];
+        p.d = d;
+        p.ne = ne;
+        p.o_node = nodes;
+        p.o_sigma = sig;
+        p.o_part = part;
+        size_t& gr = d->opt.precision == NEGF_FP32_BULK ? gr32 : gr64;
+        size_t& ad = d->opt.precision == NEGF_FP32_BULK ? ad32 : ad64;
+        p.o_gr = gr;
+        p.o_ad = ad;
+        gr += (size_t)jobs[i].n_c * Nb;
+        ad += (size_t)jobs[i].n_r * 2 * Nb;
+        nodes += ne;
+        sig += (size_t)ne * 2 * b2;
+        part += (size_t)negf::RED_SEGS * Nb;
+        max_ne = std::max(max_ne, ne);
+        max_nb = std::max(max_nb, (int)Nb);
+        w->last_max_iter[i] = d->opt.decim_max_iter;
     }
-    a.scratch = d->d_dscratch;
-    a.sigma = d->d_sigma;
-    a.iters = d->d_iters;
-    a.status = d->d_status;
-    return a;
-}
+    TRY(grow(w, w->z, nodes * 16));
+    TRY(grow(w, w->sigma, sig * 16));
+    TRY(grow(w, w->iters, nodes * 2 * 4));
+    TRY(grow(w, w->status, nodes * 4));
+    TRY(grow(w, w->coef_c, nodes * 16));
+    TRY(grow(w, w->coef_r, nodes * 3 * 8));
+    TRY(grow(w, w->T, nodes * 8));
+    TRY(grow(w, w->gr, gr64 * 16 + gr32 * 8));   // FP64 jobs first, FP32 jobs behind them
+    TRY(grow(w, w->ad, ad64 * 8 + ad32 * 4));
+    TRY(grow(w, w->part, part * 8));
+    TRY(grow(w, w->flags, (size_t)n_jobs * 2 * 4));
+    if (n_jobs > w->cap_flags) {
+        TRY(wait_prev(w));
+        if (w->h_flags) (void)hipHostFree(w->h_flags);
+        w->h_flags = nullptr;
+        w->cap_flags = 0;
+        HIPCHK(hipHostMalloc((void**)&w->h_flags, (size_t)n_jobs * 2 * sizeof(int), hipHostMallocDefault));
+        w->cap_flags = n_jobs;
+    }
+    char* gr_base = static_cast<char*>(w->gr.p);
+    char* ad_base = static_cast<char*>(w->ad.p);
 
-// The device-side launch sequence of one solve.  All arrays are device pointers.
-negf_status run_solve(negf_device* d, const negf_bias* bias, int n_c, const cx<double>* z_c, const cx<double>* w_c,
-                      int n_r, const double* E_r, const double* w_r, double* charge, double* T, double* current,
-                      hipStream_t s) {
-    HIPCHK(hipSetDevice(d->dev_id));
-    const int ne = n_c + n_r;
-    TRY(ensure_energy_ws(d, ne));
-    const int chunk = chunk_energies(d, ne);
-    TRY(ensure_store(d, chunk));
-    const int N = d->N, b = d->b, G = d->L->groups;
-    const bool f32 = d->opt.precision == NEGF_FP32_BULK;       // everything but a1/a6 in FP32
+    std::vector<negf::JobDesc> jd(n_jobs);
+    std::vector<negf::RedJob> rj(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        const JobPlan& p = plan[i];
+        const negf_job& J = jobs[i];
+        negf_device* d = p.d;
+        const bool f32 = d->opt.precision == NEGF_FP32_BULK;
+        negf::JobDesc& D = jd[i];
+        D.N = d->N;
+        D.n_c = J.n_c;
+        D.n_r = J.n_r;
+        D.K = d->K;
+        D.n_uniq = d->n_uniq;
+        D.hdiag_zero = d->hdiag_zero ? 1 : 0;
+        D.U = d->d_U;
+        D.hdiag = d->d_hdiag;
+        D.ell_map = d->d_ell_map;
+        D.cidx = d->d_cidx;
+        D.cval = d->d_cval;
+        D.ridx = d->d_ridx;
+        D.rval = d->d_rval;
+        D.z = static_cast<cx<double>*>(w->z.p) + p.o_node;
+        D.sigma = static_cast<cx<double>*>(w->sigma.p) + p.o_sigma;
+        D.gr_diag = f32 ? (void*)(gr_base + gr64 * 16 + p.o_gr * 8) : (void*)(gr_base + p.o_gr * 16);
+        D.a_diag = f32 ? (void*)(ad_base + ad64 * 8 + p.o_ad * 4) : (void*)(ad_base + p.o_ad * 8);
+        D.Tout = J.T ? J.T : static_cast<double*>(w->T.p) + p.o_node;
+        D.iters = static_cast<int*>(w->iters.p) + 2 * p.o_node;
+        D.status = static_cast<int*>(w->status.p) + p.o_node;
+        for (int l = 0; l < 2; ++l) {
+            D.period[l] = d->lead[l].period;
+            D.D[l] = d->lead[l].D;
+            D.V[l] = d->lead[l].V;
+            D.VH[l] = d->lead[l].VH;
+            D.W[l] = d->lead[l].W;
+            D.tau[l] = d->lead[l].tau;
+        }
+        negf::RedJob& R = rj[i];
+        R.Nb = d->N * d->b;
+        R.n_c = J.n_c;
+        R.n_r = J.n_r;
+        R.g_s = d->opt.g_s;
+        R.eta = d->opt.eta;
+        R.mu_L = J.bias.mu_L;
+        R.mu_R = J.bias.mu_R;
+        R.kT_L = J.bias.kT_L;
+        R.kT_R = J.bias.kT_R;
+        R.z_c = reinterpret_cast<const cx<double>*>(J.z_c);
+        R.w_c = reinterpret_cast<const cx<double>*>(J.w_c);
+        R.E_r = J.E_r;
+        R.w_r = J.w_r;
+        R.z = static_cast<cx<double>*>(w->z.p) + p.o_node;
+        R.coef_c = static_cast<cx<double>*>(w->coef_c.p) + p.o_node;
+        R.coef_r = static_cast<double*>(w->coef_r.p) + 3 * p.o_node;
+        R.gr_diag = D.gr_diag;
+        R.a_diag = D.a_diag;
+        R.T = D.Tout;
+        R.part = static_cast<double*>(w->part.p) + p.o_part;
+        R.charge = J.charge;
+        R.current = J.current;
+        R.status = D.status;
+        R.flags = static_cast<int*>(w->flags.p) + 2 * i;
+    }
+
+    // ---- groups: jobs sharing kernels (ring size, precision, decimation limits),
+    // longest chains first inside a group so that the long units start early
+    struct Group {
+        const negf::Launchers* L;
+        bool f32;
+        double tol;
+        int maxit;
+        std::vector<int> ids;
+    };
+    std::vector<Group> groups;
+    std::vector<int> order(n_jobs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plan[a].d->N > plan[b].d->N; });
+    for (int i : order) {
+        negf_device* d = plan[i].d;
+        const bool f32 = d->opt.precision == NEGF_FP32_BULK;
+        Group* g = nullptr;
+        for (auto& x : groups)
+            if (x.L == d->L && x.f32 == f32 && x.tol == d->opt.decim_tol && x.maxit == d->opt.decim_max_iter) g = &x;
+        if (!g) {
+            groups.push_back({d->L, f32, d->opt.decim_tol, d->opt.decim_max_iter, {}});
+            g = &groups.back();
+        }
+        g->ids.push_back(i);
+    }
+
+    // ---- schedules: spans and unit prefixes of every launch
+    struct Launch {
+        int kind, kt, group;
+        size_t span_at, first_at;
+        int n_spans, sides, side0;
+        long long units;
+        size_t dyn;
+    };
+    std::vector<negf::Span> spans;
+    std::vector<int> firsts;
+    std::vector<Launch> launches;
+    auto add_launch = [&](int kind, int kt, int gidx, const std::vector<negf::Span>& sp, int sides, int side0,
+                          int G, bool items, size_t dyn) -> negf_status {
+        if (sp.empty()) return NEGF_OK;
+        Launch L{kind, kt, gidx, spans.size(), firsts.size(), (int)sp.size(), sides, side0, 0, dyn};
+        long long acc = 0;
+        for (const auto& x : sp) {
+            firsts.push_back((int)acc);
+            const long long work = items ? (long long)x.cnt * jd[x.job].N : x.cnt;
+            acc += sides * ((work + G - 1) / G);
+            if (acc > (1LL << 30)) return fail(NEGF_EINVAL, "too many work units in one launch");
+            spans.push_back(x);
+        }
+        firsts.push_back((int)acc);
+        L.units = acc;
+        launches.push_back(L);
+        return NEGF_OK;
+    };
+
+    size_t scratch_need = 16, store_need = 0;
+    const size_t store_cap = w->store_cap ? w->store_cap : kDefaultStoreCap;
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        Group& g = groups[gi];
+        const int B = g.L->B, G = g.L->groups;
+        const size_t cb = g.f32 ? 8 : 16;
+        // a1: decimation at every node.  One-ring and two-ring principal layers
+        // have their own kernels; a job whose leads share the layer size runs
+        // both leads in one span (sides 2), otherwise each lead in its own launch.
+        {
+            std::vector<negf::Span> sp[2][3];   // [period - 1][both, left only, right only]
+            for (int j : g.ids) {
+                const int p0 = jd[j].period[0], p1 = jd[j].period[1];
+                if (p0 == p1) {
+                    sp[p0 - 1][0].push_back({j, 0, plan[j].ne, 0, 0});
+                } else {
+                    sp[p0 - 1][1].push_back({j, 0, plan[j].ne, 0, 0});
+                    sp[p1 - 1][2].push_back({j, 0, plan[j].ne, 0, 0});
+                }
+            }
+            for (int P = 1; P <= 2; ++P) {
+                const int kind = P == 1 ? negf::KIND_DECIMATE : negf::KIND_DECIMATE2;
+                const int Gd = P == 1 ? G : 64 / (2 * B);
+                if (P == 1 && (!sp[0][0].empty() || !sp[0][1].empty() || !sp[0][2].empty())) {
+                    const int gdec = persistent_grid(w, g.L->func[kind], 0, 1LL << 40);
+                    scratch_need = std::max(scratch_need, (size_t)gdec * G * 4 * B * B * 16);
+                }
+                for (int m = 0; m < 3; ++m)
+                    TRY(add_launch(kind, KT_DECIMATE, gi, sp[P - 1][m], m == 0 ? 2 : 1, m == 2 ? 1 : 0, Gd, false,
+                                   0));
+            }
+        }
+        if (decimation_only) continue;
+        // a3-a5: chunks of nodes whose recursion store fits the cap
+        size_t dyn = 0;
+        for (int j : g.ids) dyn = std::max(dyn, (size_t)jd[j].n_uniq * B * jd[j].K * (cb + 1));
+        size_t ji = 0;
+        int e_at = 0;
+        while (ji < g.ids.size()) {
+            std::vector<negf::Span> rec, cdg, col;
+            size_t used = 0;   // store elements (cx<T>) of this chunk
+            while (ji < g.ids.size()) {
+                const int j = g.ids[ji];
+                const size_t per = (size_t)jd[j].N * B * B;
+                const long long fit = (long long)((store_cap / cb - used) / per);
+                if (fit <= 0) {
+                    if (used == 0)
+                        return fail(NEGF_ENOMEM, "one node's recursion store (%zu bytes) exceeds the store cap",
+                                    per * cb);
+                    break;
+                }
+                const int take = (int)std::min<long long>(fit, plan[j].ne - e_at);
+                rec.push_back({j, e_at, take, 0, (long long)used});
+                const int c_hi = std::min(e_at + take, jd[j].n_c);
+                if (c_hi > e_at) cdg.push_back({j, e_at, c_hi - e_at, 0, (long long)used});
+                const int r_lo = std::max(e_at, jd[j].n_c), r_hi = e_at + take;
+                if (r_hi > r_lo)
+                    col.push_back({j, r_lo, r_hi - r_lo, 0, (long long)(used + (size_t)(r_lo - e_at) * per)});
+                used += (size_t)take * per;
+                e_at += take;
+                if (e_at >= plan[j].ne) {
+                    ++ji;
+                    e_at = 0;
+                }
+            }
+            store_need = std::max(store_need, used * cb);
+            TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, rec, 2, 0, G, false, dyn));
+            TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, G, true, 0));
+            TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, G, false,
+                           0));
+        }
+    }
+    TRY(grow(w, w->scratch, scratch_need));
+    if (store_need) {
+        TRY(grow(w, w->store_f, store_need));
+        TRY(grow(w, w->store_b, store_need));
+    }
+    const size_t n_counters = std::max<size_t>(1, launches.size());
+    TRY(grow(w, w->counters, n_counters * 4));
+
+    // ---- tables: one image [JobDesc][RedJob][Span][first], uploaded only when it
+    // differs from the last one (repeated solves of the same jobs upload nothing)
+    std::vector<char> img;
+    auto put = [&](const void* src, size_t bytes) {
+        const size_t at = (img.size() + 15) & ~size_t(15);
+        img.resize(at + bytes);
+        if (bytes) memcpy(img.data() + at, src, bytes);
+        return at;
+    };
+    const size_t o_jd = put(jd.data(), jd.size() * sizeof(negf::JobDesc));
+    const size_t o_rj = put(rj.data(), rj.size() * sizeof(negf::RedJob));
+    const size_t o_sp = put(spans.data(), spans.size() * sizeof(negf::Span));
+    const size_t o_fi = put(firsts.data(), firsts.size() * sizeof(int));
+    if (img != w->last_tables || !w->tables.p) {
+        TRY(grow(w, w->tables, img.size()));
+        TRY(wait_prev(w));
+        HIPCHK(hipMemcpy(w->tables.p, img.data(), img.size(), hipMemcpyHostToDevice));
+        w->last_tables.swap(img);
+    }
+    char* tab = static_cast<char*>(w->tables.p);
+    const negf::JobDesc* d_jobs = reinterpret_cast<const negf::JobDesc*>(tab + o_jd);
+    const negf::RedJob* d_red = reinterpret_cast<const negf::RedJob*>(tab + o_rj);
+    const negf::Span* d_spans = reinterpret_cast<const negf::Span*>(tab + o_sp);
+    const int* d_first = reinterpret_cast<const int*>(tab + o_fi);
+
     hipEvent_t ev;
+    ev_begin(w, s, &ev);
+    hipLaunchKernelGGL(negf::k_fill_int, dim3((unsigned)((n_counters + 255) / 256)), dim3(256), 0, s,
+                       static_cast<int*>(w->counters.p), (int)n_counters, 0);
+    hipLaunchKernelGGL(negf::k_nodes, dim3((max_ne + 255) / 256, n_jobs), dim3(256), 0, s, d_red,
+                       static_cast<int*>(w->status.p), (int)nodes);
+    ev_end(w, KT_REDUCE, s, ev);
 
-    ev_begin(d, KT_REDUCE, s, &ev);
-    hipLaunchKernelGGL(negf::k_nodes, dim3((ne + 255) / 256), dim3(256), 0, s, z_c, n_c, E_r, n_r, d->opt.eta, d->d_z);
-    hipLaunchKernelGGL(k_fill_int, dim3((ne + 255) / 256), dim3(256), 0, s, d->d_status, ne, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, d->d_flags, 1, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, d->d_flags + 1, 1, 0x7fffffff);
-    ev_end(d, KT_REDUCE, s, ev);
-
-    // a1: lead self-energies for every node, both leads in one launch
-    ev_begin(d, KT_DECIMATE, s, &ev);
-    {
-        negf::DecArgs a = dec_args(d, ne, -1);
-        d->L->decimate(a, 2 * ((ne + G - 1) / G), s);
-    }
-    ev_end(d, KT_DECIMATE, s, ev);
-    hipLaunchKernelGGL(negf::k_status, dim3((ne + 255) / 256), dim3(256), 0, s, d->d_status, ne, d->d_flags,
-                       d->d_flags + 1);
-
-    negf::RgfArgs A{};
-    A.N = N;
-    A.b = b;
-    A.n_c = n_c;
-    A.K = d->K;
-    A.n_uniq = d->n_uniq;
-    A.ell_map = d->d_ell_map;
-    A.hdiag_zero = d->hdiag_zero ? 1 : 0;
-    A.U = d->d_U;
-    A.hdiag = d->d_hdiag;
-    A.cidx = d->d_cidx;
-    A.cval = d->d_cval;
-    A.ridx = d->d_ridx;
-    A.rval = d->d_rval;
-    A.z = d->d_z;
-    A.sigma = d->d_sigma;
-    A.store_f = d->d_store_f;
-    A.store_b = d->d_store_b;
-    A.gr_diag = d->d_gr;
-    A.a_diag = d->d_ad;
-    A.Tout = d->d_T;
-
-    for (int e0 = 0; e0 < ne; e0 += chunk) {
-        const int cn = std::min(chunk, ne - e0);
-        A.e0 = e0;
-        A.ne = cn;
-        // a3-a4 recursions: both directions of every node of the chunk
-        ev_begin(d, KT_RECUR, s, &ev);
-        const int wv = (cn + G - 1) / G;
-        (f32 ? d->L->recur32 : d->L->recur64)(A, 2 * wv, s);
-        ev_end(d, KT_RECUR, s, ev);
-        // contour nodes of the chunk: diagonal blocks
-        const int c_end = std::min(e0 + cn, n_c);
-        if (c_end > e0) {
-            const int nc = c_end - e0;
-            const long long items = (long long)nc * N;
-            ev_begin(d, KT_CDIAG, s, &ev);
-            (f32 ? d->L->cdiag32 : d->L->cdiag64)(A, nc, (int)((items + G - 1) / G), s);
-            ev_end(d, KT_CDIAG, s, ev);
-        }
-        // real-axis nodes of the chunk: lead columns, A_l diagonals, T
-        const int r0 = std::max(e0, n_c);
-        if (e0 + cn > r0) {
-            const int nr = e0 + cn - r0;
-            ev_begin(d, KT_COLUMN, s, &ev);
-            (f32 ? d->L->column32 : d->L->column64)(A, r0, nr, 2 * ((nr + G - 1) / G), s);
-            ev_end(d, KT_COLUMN, s, ev);
-        }
+    for (size_t li = 0; li < launches.size(); ++li) {
+        const Launch& L = launches[li];
+        const Group& g = groups[L.group];
+        negf::Sched S{};
+        S.jobs = d_jobs;
+        S.spans = d_spans + L.span_at;
+        S.first = d_first + L.first_at;
+        S.n_spans = L.n_spans;
+        S.sides = L.sides;
+        S.side0 = L.side0;
+        S.counter = static_cast<int*>(w->counters.p) + li;
+        S.store_f = w->store_f.p;
+        S.store_b = w->store_b.p;
+        S.scratch = static_cast<cx<double>*>(w->scratch.p);
+        S.tol = g.tol;
+        S.maxit = g.maxit;
+        const int grid = persistent_grid(w, g.L->func[L.kind], L.dyn, L.units);
+        ev_begin(w, s, &ev);
+        g.L->launch[L.kind](S, grid, L.dyn, s);
+        ev_end(w, L.kt, s, ev);
     }
 
-    // a6: weighted energy sums
-    negf::RedArgs R{};
-    R.Nb = N * b;
-    R.n_c = n_c;
-    R.n_r = n_r;
-    R.g_s = d->opt.g_s;
-    R.mu_L = bias->mu_L;
-    R.mu_R = bias->mu_R;
-    R.kT_L = bias->kT_L;
-    R.kT_R = bias->kT_R;
-    R.z_c = z_c;
-    R.w_c = w_c;
-    R.E_r = E_r;
-    R.w_r = w_r;
-    R.coef_c = d->d_coef_c;
-    R.coef_r = d->d_coef_r;
-    R.gr_diag = d->d_gr;
-    R.a_diag = d->d_ad;
-    R.T = d->d_T;
-    R.charge = charge;
-    R.current = current;
-    R.flags = d->d_flags;
-    ev_begin(d, KT_REDUCE, s, &ev);
-    hipLaunchKernelGGL(negf::k_coef, dim3((ne + 255) / 256), dim3(256), 0, s, R);
-    if (!d->d_part) TRY(dalloc(d, &d->d_part, (size_t)negf::RED_SEGS * R.Nb * 8));
-    const dim3 rgrid((R.Nb + 255) / 256, negf::RED_SEGS);
-    if (f32)
-        hipLaunchKernelGGL((negf::k_reduce_part<float, float>), rgrid, dim3(256), 0, s, R, d->d_part);
-    else
-        hipLaunchKernelGGL((negf::k_reduce_part<double, double>), rgrid, dim3(256), 0, s, R, d->d_part);
-    hipLaunchKernelGGL(negf::k_reduce_final, dim3((R.Nb + 255) / 256), dim3(256), 0, s, R, d->d_part);
-    if (n_r > 0)
-        hipLaunchKernelGGL(negf::k_current, dim3(1), dim3(64), 0, s, R);
-    else if (current)
-        hipLaunchKernelGGL(k_zero_double, dim3(1), dim3(1), 0, s, current);
-    if (T && n_r > 0) HIPCHK(hipMemcpyAsync(T, d->d_T, (size_t)n_r * 8, hipMemcpyDeviceToDevice, s));
-    ev_end(d, KT_REDUCE, s, ev);
-    HIPCHK(hipMemcpyAsync(d->h_flags, d->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    // ---- a6: weighted energy sums (status folded into the flags by k_coef)
+    ev_begin(w, s, &ev);
+    hipLaunchKernelGGL(negf::k_coef, dim3((max_ne + 255) / 256, n_jobs), dim3(256), 0, s, d_red);
+    if (!decimation_only) {
+        for (int i = 0; i < n_jobs; ++i) {
+            const dim3 rgrid((unsigned)((plan[i].d->N * plan[i].d->b + 255) / 256), negf::RED_SEGS, 1);
+            if (plan[i].d->opt.precision == NEGF_FP32_BULK)
+                hipLaunchKernelGGL((negf::k_reduce_part<float, float>), rgrid, dim3(256), 0, s, d_red + i);
+            else
+                hipLaunchKernelGGL((negf::k_reduce_part<double, double>), rgrid, dim3(256), 0, s, d_red + i);
+        }
+        hipLaunchKernelGGL(negf::k_reduce_final, dim3((max_nb + 255) / 256, n_jobs), dim3(256), 0, s, d_red);
+        hipLaunchKernelGGL(negf::k_current, dim3(n_jobs), dim3(64), 0, s, d_red);
+    }
+    ev_end(w, KT_REDUCE, s, ev);
+    HIPCHK(hipMemcpyAsync(w->h_flags, w->flags.p, (size_t)n_jobs * 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipGetLastError());
-    d->last_stream = s;
-    d->last_ne = ne;
+    HIPCHK(hipEventRecord(w->done, s));
+    w->last_n_jobs = n_jobs;
     return NEGF_OK;
 }
 
-negf_status finish(negf_device* d) {
-    HIPCHK(hipStreamSynchronize(d->last_stream));
-    ev_collect(d);
-    const int fl = d->h_flags[0];
-    if (fl & 1)
-        return fail(NEGF_ENOCONV, "lead decimation did not converge in %d steps (first energy index %d)",
-                    d->opt.decim_max_iter, d->h_flags[1]);
-    if (fl & 2) return fail(NEGF_ESINGULAR, "non-finite charge or current (singular block or overflow)");
+negf_status finish(negf_workspace* w, int* failed_job) {
+    if (failed_job) *failed_job = -1;
+    TRY(wait_prev(w));
+    ev_collect(w);
+    const int n = w->last_n_jobs;
+    w->last_n_jobs = 0;
+    for (int j = 0; j < n; ++j) {
+        const int fl = w->h_flags[2 * j];
+        if (!fl) continue;
+        if (failed_job) *failed_job = j;
+        if (fl & 1)
+            return fail(NEGF_ENOCONV, "job %d: lead decimation did not converge in %d steps (first node %d)", j,
+                        w->last_max_iter[j], w->h_flags[2 * j + 1]);
+        return fail(NEGF_ESINGULAR, "job %d: non-finite charge or current (singular block or overflow)", j);
+    }
+    return NEGF_OK;
+}
+
+negf_status ws_create(negf_workspace** out, size_t store_bytes) {
+    negf_workspace* w = new negf_workspace();
+    w->store_cap = store_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&w->dev_id) != hipSuccess || hipGetDeviceProperties(&prop, w->dev_id) != hipSuccess) {
+        delete w;
+        return fail(NEGF_EHIP, "no HIP device");
+    }
+    w->cus = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&w->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete w;
+        return fail(NEGF_EHIP, "stream creation failed");
+    }
+    if (hipEventCreateWithFlags(&w->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(w->own_stream);
+        delete w;
+        return fail(NEGF_EHIP, "event creation failed");
+    }
+    if (hipHostMalloc((void**)&w->h_flags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipEventDestroy(w->done);
+        (void)hipStreamDestroy(w->own_stream);
+        delete w;
+        return fail(NEGF_ENOMEM, "pinned flag buffer");
+    }
+    w->cap_flags = 1;
+    w->h_flags[0] = w->h_flags[1] = 0;
+    *out = w;
+    return NEGF_OK;
+}
+
+void ws_destroy(negf_workspace* w) {
+    if (!w) return;
+    (void)hipSetDevice(w->dev_id);
+    (void)hipEventSynchronize(w->done);
+    for (auto& e : w->pending) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,  &w->iters,      &w->status,
+                    &w->coef_c, &w->coef_r,   &w->T,       &w->gr,     &w->ad,         &w->part,
+                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc,
+                    &w->in_Er,  &w->in_wr,    &w->out_charge, &w->out_T, &w->out_cur};
+    for (DBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (w->h_flags) (void)hipHostFree(w->h_flags);
+    if (w->done) (void)hipEventDestroy(w->done);
+    if (w->own_stream) (void)hipStreamDestroy(w->own_stream);
+    delete w;
+}
+
+// Host-pointer batch: stage the inputs, solve on the workspace stream, copy the
+// outputs back.  `outs` (optional, single-job calls only) receives the
+// energy-resolved arrays of job 0.
+negf_status solve_host(negf_workspace* w, int n_jobs, const negf_job* jobs, const negf_outputs* outs) {
+    HIPCHK(hipSetDevice(w->dev_id));
+    size_t nc = 0, nr = 0, nb = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        nc += jobs[i].n_c;
+        nr += jobs[i].n_r;
+        nb += (size_t)jobs[i].dev->N * jobs[i].dev->b;
+    }
+    TRY(grow(w, w->in_zc, nc * 16));
+    TRY(grow(w, w->in_wc, nc * 16));
+    TRY(grow(w, w->in_Er, nr * 8));
+    TRY(grow(w, w->in_wr, nr * 8));
+    TRY(grow(w, w->out_charge, nb * 8));
+    TRY(grow(w, w->out_T, nr * 8));
+    TRY(grow(w, w->out_cur, (size_t)n_jobs * 8));
+    hipStream_t s = w->own_stream;
+    std::vector<negf_job> dj(jobs, jobs + n_jobs);
+    size_t oc = 0, orr = 0, ob = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        negf_job& j = dj[i];
+        negf_c64* zc = static_cast<negf_c64*>(w->in_zc.p) + oc;
+        negf_c64* wc = static_cast<negf_c64*>(w->in_wc.p) + oc;
+        double* Er = static_cast<double*>(w->in_Er.p) + orr;
+        double* wr = static_cast<double*>(w->in_wr.p) + orr;
+        if (j.n_c) {
+            HIPCHK(hipMemcpy(zc, jobs[i].z_c, (size_t)j.n_c * 16, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(wc, jobs[i].w_c, (size_t)j.n_c * 16, hipMemcpyHostToDevice));
+        }
+        if (j.n_r) {
+            HIPCHK(hipMemcpy(Er, jobs[i].E_r, (size_t)j.n_r * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(wr, jobs[i].w_r, (size_t)j.n_r * 8, hipMemcpyHostToDevice));
+        }
+        j.z_c = zc;
+        j.w_c = wc;
+        j.E_r = Er;
+        j.w_r = wr;
+        j.charge = static_cast<double*>(w->out_charge.p) + ob;
+        j.T = static_cast<double*>(w->out_T.p) + orr;
+        j.current = static_cast<double*>(w->out_cur.p) + i;
+        oc += j.n_c;
+        orr += j.n_r;
+        ob += (size_t)j.dev->N * j.dev->b;
+    }
+    TRY(enqueue(w, n_jobs, dj.data(), s));
+    const negf_status st = finish(w, nullptr);
+    const std::string msg = g_err;
+    // outputs are copied on a device-side error status too, for inspection
+    for (int i = 0; i < n_jobs; ++i) {
+        const negf_job& j = dj[i];
+        const size_t Nb = (size_t)j.dev->N * j.dev->b;
+        HIPCHK(hipMemcpy(jobs[i].charge, j.charge, Nb * 8, hipMemcpyDeviceToHost));
+        if (jobs[i].T && j.n_r) HIPCHK(hipMemcpy(jobs[i].T, j.T, (size_t)j.n_r * 8, hipMemcpyDeviceToHost));
+        if (jobs[i].current) HIPCHK(hipMemcpy(jobs[i].current, j.current, 8, hipMemcpyDeviceToHost));
+    }
+    if (outs) {   // with one job, its arrays start at offset 0 of their buffers
+        negf_device* d = dj[0].dev;
+        const negf_job& j = dj[0];
+        const size_t Nb = (size_t)d->N * d->b;
+        const bool f32 = d->opt.precision == NEGF_FP32_BULK;
+        if (outs->gr_diag && j.n_c) {
+            if (f32) {
+                std::vector<float> tmp((size_t)j.n_c * Nb * 2);
+                HIPCHK(hipMemcpy(tmp.data(), w->gr.p, tmp.size() * 4, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < (size_t)j.n_c * Nb; ++i)
+                    outs->gr_diag[i] = negf_c64{tmp[2 * i], tmp[2 * i + 1]};
+            } else {
+                HIPCHK(hipMemcpy(outs->gr_diag, w->gr.p, (size_t)j.n_c * Nb * 16, hipMemcpyDeviceToHost));
+            }
+        }
+        if ((outs->al_diag || outs->ar_diag) && j.n_r) {
+            std::vector<double> ad((size_t)j.n_r * 2 * Nb);
+            if (f32) {
+                std::vector<float> tmp(ad.size());
+                HIPCHK(hipMemcpy(tmp.data(), w->ad.p, tmp.size() * 4, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < ad.size(); ++i) ad[i] = tmp[i];
+            } else {
+                HIPCHK(hipMemcpy(ad.data(), w->ad.p, ad.size() * 8, hipMemcpyDeviceToHost));
+            }
+            for (int q = 0; q < j.n_r; ++q) {
+                if (outs->al_diag) memcpy(outs->al_diag + (size_t)q * Nb, ad.data() + ((size_t)q * 2 + 0) * Nb, Nb * 8);
+                if (outs->ar_diag) memcpy(outs->ar_diag + (size_t)q * Nb, ad.data() + ((size_t)q * 2 + 1) * Nb, Nb * 8);
+            }
+        }
+        if (outs->decim_iters)
+            HIPCHK(hipMemcpy(outs->decim_iters, w->iters.p, (size_t)(j.n_c + j.n_r) * 2 * 4, hipMemcpyDeviceToHost));
+    }
+    g_err = msg;
+    return st;
+}
+
+negf_job make_job(negf_device* d, const negf_bias* bias, int n_c, const negf_c64* z_c, const negf_c64* w_c, int n_r,
+                  const double* E_r, const double* w_r, double* charge, double* T, double* current) {
+    negf_job j{};
+    j.dev = d;
+    if (bias) j.bias = *bias;
+    j.n_c = n_c;
+    j.z_c = z_c;
+    j.w_c = w_c;
+    j.n_r = n_r;
+    j.E_r = E_r;
+    j.w_r = w_r;
+    j.charge = charge;
+    j.T = T;
+    j.current = current;
+    return j;
+}
+
+negf_status check_batch(negf_workspace* w, int n_jobs, const negf_job* jobs, bool host) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    if (n_jobs < 1 || !jobs) return fail(NEGF_EINVAL, "no jobs");
+    for (int i = 0; i < n_jobs; ++i) {
+        TRY(check_job(jobs[i], i, host));
+        if (jobs[i].dev->dev_id != w->dev_id) return fail(NEGF_EINVAL, "job %d lives on another HIP device", i);
+    }
     return NEGF_OK;
 }
 
@@ -499,40 +814,23 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
     const negf::Launchers* L = launchers_for(b);
     if (!L) return fail(NEGF_EINVAL, "no kernels for ring size %d", b);
 
-    negf_device* d = new negf_device();
-    d->N = n_rings;
-    d->b = b;
-    d->opt = o;
-    d->L = L;
-    auto bail = [&](negf_status s) { std::string m = g_err; negf_destroy(d); g_err = m; return s; };
-    if (hipGetDevice(&d->dev_id) != hipSuccess) return bail(fail(NEGF_EHIP, "no HIP device"));
-
-    // hdiag
-    d->hdiag_zero = true;
-    for (size_t i = 0; i < (size_t)n_rings * b2; ++i)
-        if (h_diag[i].re != 0.0 || h_diag[i].im != 0.0) { d->hdiag_zero = false; break; }
-    negf_status s;
-    if ((s = dalloc(d, &d->d_hdiag, (size_t)n_rings * b2 * 16)) != NEGF_OK) return bail(s);
-    if (hipMemcpy(d->d_hdiag, h_diag, (size_t)n_rings * b2 * 16, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(NEGF_EHIP, "copy of h_diag failed"));
-    if ((s = dalloc(d, &d->d_U, (size_t)n_rings * b * 8)) != NEGF_OK) return bail(s);
-    if (hipMemset(d->d_U, 0, (size_t)n_rings * b * 8) != hipSuccess) return bail(fail(NEGF_EHIP, "memset U"));
-
-    // couplings: distinct blocks as column- and row-ELL with a common width K, plus
-    // the map ring coupling -> distinct block (periodic structures have few blocks)
+    // couplings: the distinct blocks as column- and row-ELL of a common width K,
+    // plus the map ring coupling -> distinct block (periodic tubes have few)
     const int nc = std::max(0, n_rings - 1);
     std::vector<int> ell_map((size_t)std::max(1, nc), 0);
-    std::vector<int> uniq;   // index n of the first coupling of each distinct block
+    std::vector<int> uniq;   // ring index n of the first coupling of each distinct block
     for (int n = 0; n < nc; ++n) {
         const negf_c64* H = h_up + (size_t)n * b2;
         int found = -1;
         for (size_t u = 0; u < uniq.size() && found < 0; ++u)
             if (memcmp(H, h_up + (size_t)uniq[u] * b2, b2 * sizeof(negf_c64)) == 0) found = (int)u;
-        if (found < 0) { found = (int)uniq.size(); uniq.push_back(n); }
+        if (found < 0) {
+            found = (int)uniq.size();
+            uniq.push_back(n);
+        }
         ell_map[n] = found;
     }
     const int nu = std::max<int>(1, (int)uniq.size());
-    d->n_uniq = nu;
     int K = 1;
     for (int u = 0; u < (int)uniq.size(); ++u) {
         const negf_c64* H = h_up + (size_t)uniq[u] * b2;
@@ -545,11 +843,40 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
             K = std::max(K, std::max(cc, rc));
         }
     }
-    d->K = K;
     const size_t ell = (size_t)nu * b * K;
     if (ell * (sizeof(negf_c64) + 1) > 32768)
-        return bail(fail(NEGF_EINVAL, "coupling table of %d distinct blocks (width %d) exceeds the 32 KiB LDS table",
-                         nu, K));
+        return fail(NEGF_EINVAL, "coupling table of %d distinct blocks (width %d) exceeds the 32 KiB LDS table", nu,
+                    K);
+
+    negf_device* d = new negf_device();
+    d->N = n_rings;
+    d->b = b;
+    d->opt = o;
+    d->L = L;
+    d->K = K;
+    d->n_uniq = nu;
+    auto bail = [&](negf_status s) {
+        const std::string m = g_err;
+        negf_destroy(d);
+        g_err = m;
+        return s;
+    };
+    if (hipGetDevice(&d->dev_id) != hipSuccess) return bail(fail(NEGF_EHIP, "no HIP device"));
+    negf_status s;
+    if ((s = ws_create(&d->ws, o.workspace_bytes ? o.workspace_bytes / 2 : 0)) != NEGF_OK) return bail(s);
+
+    d->hdiag_zero = true;
+    for (size_t i = 0; i < (size_t)n_rings * b2; ++i)
+        if (h_diag[i].re != 0.0 || h_diag[i].im != 0.0) {
+            d->hdiag_zero = false;
+            break;
+        }
+    if ((s = dalloc(d, &d->d_hdiag, (size_t)n_rings * b2 * 16)) != NEGF_OK) return bail(s);
+    if (hipMemcpy(d->d_hdiag, h_diag, (size_t)n_rings * b2 * 16, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(NEGF_EHIP, "copy of h_diag failed"));
+    if ((s = dalloc(d, &d->d_U, (size_t)n_rings * b * 8)) != NEGF_OK) return bail(s);
+    if (hipMemset(d->d_U, 0, (size_t)n_rings * b * 8) != hipSuccess) return bail(fail(NEGF_EHIP, "memset U"));
+
     std::vector<int> cidx(ell, 0), ridx(ell, 0);
     std::vector<negf_c64> cval(ell, negf_c64{0, 0}), rval(ell, negf_c64{0, 0});
     for (int u = 0; u < (int)uniq.size(); ++u) {
@@ -583,15 +910,14 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
         hipMemcpy(d->d_rval, rval.data(), ell * 16, hipMemcpyHostToDevice) != hipSuccess)
         return bail(fail(NEGF_EHIP, "copy of couplings failed"));
 
-    // leads
     const negf_lead* leads[2] = {left, right};
     for (int l = 0; l < 2; ++l) {
         LeadDev& ld = d->lead[l];
         const negf_lead* src = leads[l];
         ld.period = src->period;
         ld.h_diag.assign(src->h_diag, src->h_diag + (size_t)src->period * b2);
-        std::vector<negf_c64> V(src->h_up, src->h_up + b2), VH(b2), W(src->h_up + (size_t)(src->period - 1) * b2,
-                                                                     src->h_up + (size_t)src->period * b2);
+        std::vector<negf_c64> V(src->h_up, src->h_up + b2), VH(b2),
+            W(src->h_up + (size_t)(src->period - 1) * b2, src->h_up + (size_t)src->period * b2);
         for (int i = 0; i < b; ++i)
             for (int j = 0; j < b; ++j) {
                 const negf_c64 v = V[(size_t)j * b + i];
@@ -609,14 +935,6 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
             return bail(fail(NEGF_EHIP, "copy of lead blocks failed"));
         if ((s = upload_lead_D(d, l)) != NEGF_OK) return bail(s);
     }
-    if (hipStreamCreateWithFlags(&d->own_stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(NEGF_EHIP, "stream creation failed"));
-    if ((s = dalloc(d, &d->d_flags, 2 * sizeof(int))) != NEGF_OK) return bail(s);
-    if (hipHostMalloc((void**)&d->h_flags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
-        return bail(fail(NEGF_ENOMEM, "pinned flag buffer"));
-    d->h_flags[0] = 0;
-    d->h_flags[1] = 0;
-    d->last_stream = d->own_stream;
     *out = d;
     return NEGF_OK;
 }
@@ -658,78 +976,27 @@ negf_status negf_set_potential_dev(negf_device* d, const double* U_dev, double U
 negf_status negf_solve_dev(negf_device* d, const negf_bias* bias, int n_c, const negf_c64* z_c, const negf_c64* w_c,
                            int n_r, const double* E_r, const double* w_r, double* charge, double* T, double* current,
                            void* hip_stream) {
-    TRY(check_solve_args(d, bias, n_c, z_c, w_c, n_r, E_r, w_r, charge));
-    return run_solve(d, bias, n_c, reinterpret_cast<const cx<double>*>(z_c), reinterpret_cast<const cx<double>*>(w_c),
-                     n_r, E_r, w_r, charge, T, current, (hipStream_t)hip_stream);
+    if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
+    if (!bias) return fail(NEGF_EINVAL, "bias is NULL");
+    const negf_job j = make_job(d, bias, n_c, z_c, w_c, n_r, E_r, w_r, charge, T, current);
+    TRY(check_job(j, 0, false));
+    return enqueue(d->ws, 1, &j, (hipStream_t)hip_stream);
 }
 
 negf_status negf_sync(negf_device* d) {
     if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
     HIPCHK(hipSetDevice(d->dev_id));
-    return finish(d);
+    return finish(d->ws, nullptr);
 }
 
 negf_status negf_solve_ex(negf_device* d, const negf_bias* bias, int n_c, const negf_c64* z_c, const negf_c64* w_c,
                           int n_r, const double* E_r, const double* w_r, const negf_outputs* out) {
     if (!out) return fail(NEGF_EINVAL, "outputs are NULL");
-    TRY(check_solve_args(d, bias, n_c, z_c, w_c, n_r, E_r, w_r, out->charge));
-    for (int i = 0; i < n_c; ++i)
-        if (!std::isfinite(z_c[i].re) || !std::isfinite(z_c[i].im) || !std::isfinite(w_c[i].re) ||
-            !std::isfinite(w_c[i].im))
-            return fail(NEGF_EINVAL, "contour node %d is not finite", i);
-    for (int i = 0; i < n_r; ++i)
-        if (!std::isfinite(E_r[i]) || !std::isfinite(w_r[i])) return fail(NEGF_EINVAL, "real node %d is not finite", i);
-    HIPCHK(hipSetDevice(d->dev_id));
-    TRY(ensure_io(d, n_c, n_r));
-    const size_t Nb = (size_t)d->N * d->b;
-    if (!d->d_out_charge) {
-        TRY(dalloc(d, &d->d_out_cur, 8));
-        TRY(dalloc(d, &d->d_out_charge, Nb * 8));
-    }
-    hipStream_t s = d->own_stream;
-    if (n_c) {
-        HIPCHK(hipMemcpyAsync(d->d_in_zc, z_c, (size_t)n_c * 16, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d->d_in_wc, w_c, (size_t)n_c * 16, hipMemcpyHostToDevice, s));
-    }
-    if (n_r) {
-        HIPCHK(hipMemcpyAsync(d->d_in_Er, E_r, (size_t)n_r * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d->d_in_wr, w_r, (size_t)n_r * 8, hipMemcpyHostToDevice, s));
-    }
-    TRY(run_solve(d, bias, n_c, d->d_in_zc, d->d_in_wc, n_r, d->d_in_Er, d->d_in_wr, d->d_out_charge, nullptr,
-                  d->d_out_cur, s));
-    negf_status st = finish(d);
-    // outputs are copied even on a device-side error status so that callers can inspect them
-    HIPCHK(hipMemcpy(out->charge, d->d_out_charge, Nb * 8, hipMemcpyDeviceToHost));
-    if (out->current) HIPCHK(hipMemcpy(out->current, d->d_out_cur, 8, hipMemcpyDeviceToHost));
-    if (out->T && n_r) HIPCHK(hipMemcpy(out->T, d->d_T, (size_t)n_r * 8, hipMemcpyDeviceToHost));
-    const bool f32 = d->opt.precision == NEGF_FP32_BULK;
-    const bool ad32 = f32;
-    if (out->gr_diag && n_c) {
-        if (f32) {
-            std::vector<float> tmp((size_t)n_c * Nb * 2);
-            HIPCHK(hipMemcpy(tmp.data(), d->d_gr, tmp.size() * 4, hipMemcpyDeviceToHost));
-            for (size_t i = 0; i < (size_t)n_c * Nb; ++i) out->gr_diag[i] = negf_c64{tmp[2 * i], tmp[2 * i + 1]};
-        } else {
-            HIPCHK(hipMemcpy(out->gr_diag, d->d_gr, (size_t)n_c * Nb * 16, hipMemcpyDeviceToHost));
-        }
-    }
-    if ((out->al_diag || out->ar_diag) && n_r) {
-        std::vector<double> ad((size_t)n_r * 2 * Nb);
-        if (ad32) {
-            std::vector<float> tmp(ad.size());
-            HIPCHK(hipMemcpy(tmp.data(), d->d_ad, tmp.size() * 4, hipMemcpyDeviceToHost));
-            for (size_t i = 0; i < ad.size(); ++i) ad[i] = tmp[i];
-        } else {
-            HIPCHK(hipMemcpy(ad.data(), d->d_ad, ad.size() * 8, hipMemcpyDeviceToHost));
-        }
-        for (int q = 0; q < n_r; ++q) {
-            if (out->al_diag) memcpy(out->al_diag + (size_t)q * Nb, ad.data() + ((size_t)q * 2 + 0) * Nb, Nb * 8);
-            if (out->ar_diag) memcpy(out->ar_diag + (size_t)q * Nb, ad.data() + ((size_t)q * 2 + 1) * Nb, Nb * 8);
-        }
-    }
-    if (out->decim_iters)
-        HIPCHK(hipMemcpy(out->decim_iters, d->d_iters, (size_t)(n_c + n_r) * 2 * 4, hipMemcpyDeviceToHost));
-    return st;
+    if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
+    if (!bias) return fail(NEGF_EINVAL, "bias is NULL");
+    const negf_job j = make_job(d, bias, n_c, z_c, w_c, n_r, E_r, w_r, out->charge, out->T, out->current);
+    TRY(check_job(j, 0, true));
+    return solve_host(d->ws, 1, &j, out);
 }
 
 negf_status negf_solve(negf_device* d, const negf_bias* bias, int n_c, const negf_c64* z_c, const negf_c64* w_c,
@@ -745,69 +1012,75 @@ negf_status negf_lead_self_energy(negf_device* d, int lead, int n, const negf_c6
     if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
     if (lead != NEGF_LEAD_LEFT && lead != NEGF_LEAD_RIGHT) return fail(NEGF_EINVAL, "lead must be 0 or 1");
     if (n < 1) return fail(NEGF_EINVAL, "n = %d < 1", n);
+    if (n > (1 << 26)) return fail(NEGF_EINVAL, "n = %d too large", n);
     if (!z || !sigma) return fail(NEGF_EINVAL, "z or sigma is NULL");
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(z[i].re) || !std::isfinite(z[i].im)) return fail(NEGF_EINVAL, "z[%d] not finite", i);
+    negf_workspace* w = d->ws;
     HIPCHK(hipSetDevice(d->dev_id));
-    TRY(ensure_energy_ws(d, n));
-    hipStream_t s = d->own_stream;
-    const int b = d->b, G = d->L->groups;
-    HIPCHK(hipMemcpyAsync(d->d_z, z, (size_t)n * 16, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, d->d_status, n, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, d->d_flags, 1, 0);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, d->d_flags + 1, 1, 0x7fffffff);
-    negf::DecArgs a = dec_args(d, n, lead);
-    d->L->decimate(a, (n + G - 1) / G, s);
-    hipLaunchKernelGGL(negf::k_status, dim3((n + 255) / 256), dim3(256), 0, s, d->d_status, n, d->d_flags,
-                       d->d_flags + 1);
-    HIPCHK(hipMemcpyAsync(d->h_flags, d->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    const size_t b2 = (size_t)b * b;
+    TRY(grow(w, w->in_zc, (size_t)n * 16));
+    TRY(grow(w, w->out_charge, (size_t)d->N * d->b * 8));
+    hipStream_t s = w->own_stream;
+    HIPCHK(hipMemcpy(w->in_zc.p, z, (size_t)n * 16, hipMemcpyHostToDevice));
+    // the nodes enter as contour nodes (used as given); only the decimation runs
+    const negf_bias b{0.0, 0.0, 1.0, 1.0};
+    const negf_job j = make_job(d, &b, n, static_cast<negf_c64*>(w->in_zc.p), static_cast<negf_c64*>(w->in_zc.p), 0,
+                                nullptr, nullptr, static_cast<double*>(w->out_charge.p), nullptr, nullptr);
+    TRY(enqueue(w, 1, &j, s, true));
+    const negf_status st = finish(w, nullptr);
+    const std::string msg = g_err;
+    const size_t b2 = (size_t)d->b * d->b;
     std::vector<negf_c64> all((size_t)n * 2 * b2);
-    HIPCHK(hipMemcpy(all.data(), d->d_sigma, all.size() * 16, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(all.data(), w->sigma.p, all.size() * 16, hipMemcpyDeviceToHost));
     for (int i = 0; i < n; ++i) memcpy(sigma + (size_t)i * b2, all.data() + ((size_t)i * 2 + lead) * b2, b2 * 16);
     if (iters) {
         std::vector<int> it((size_t)n * 2);
-        HIPCHK(hipMemcpy(it.data(), d->d_iters, it.size() * 4, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(it.data(), w->iters.p, it.size() * 4, hipMemcpyDeviceToHost));
         for (int i = 0; i < n; ++i) iters[i] = it[(size_t)i * 2 + lead];
     }
-    if (d->h_flags[0] & 1)
-        return fail(NEGF_ENOCONV, "lead decimation did not converge in %d steps (first node %d)",
-                    d->opt.decim_max_iter, d->h_flags[1]);
+    g_err = msg;
+    return st;
+}
+
+negf_status negf_workspace_set_profiling(negf_workspace* w, int enable) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    w->prof = enable != 0;
+    for (int k = 0; k < KT_COUNT; ++k) {
+        w->ms[k] = 0;
+        w->calls[k] = 0;
+    }
     return NEGF_OK;
 }
 
-negf_status negf_set_profiling(negf_device* d, int enable) {
-    if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
-    d->prof = enable != 0;
-    for (int k = 0; k < KT_COUNT; ++k) { d->ms[k] = 0; d->calls[k] = 0; }
-    return NEGF_OK;
-}
-
-negf_status negf_kernel_times(negf_device* d, const char** names, double* ms, int* calls, int* count) {
-    if (!d || !count) return fail(NEGF_EINVAL, "NULL argument");
+negf_status negf_workspace_kernel_times(negf_workspace* w, const char** names, double* ms, int* calls, int* count) {
+    if (!w || !count) return fail(NEGF_EINVAL, "NULL argument");
     const int n = std::min(*count, (int)KT_COUNT);
     for (int k = 0; k < n; ++k) {
         if (names) names[k] = kKernelNames[k];
-        if (ms) ms[k] = d->ms[k];
-        if (calls) calls[k] = d->calls[k];
+        if (ms) ms[k] = w->ms[k];
+        if (calls) calls[k] = w->calls[k];
     }
     *count = KT_COUNT;
     return NEGF_OK;
 }
 
-size_t negf_device_bytes(const negf_device* d) { return d ? d->bytes : 0; }
+negf_status negf_set_profiling(negf_device* d, int enable) {
+    if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
+    return negf_workspace_set_profiling(d->ws, enable);
+}
+
+negf_status negf_kernel_times(negf_device* d, const char** names, double* ms, int* calls, int* count) {
+    if (!d) return fail(NEGF_EINVAL, "NULL argument");
+    return negf_workspace_kernel_times(d->ws, names, ms, calls, count);
+}
+
+size_t negf_device_bytes(const negf_device* d) { return d ? d->bytes + (d->ws ? d->ws->bytes : 0) : 0; }
 
 void negf_destroy(negf_device* d) {
     if (!d) return;
     (void)hipSetDevice(d->dev_id);
-    if (d->own_stream) (void)hipStreamSynchronize(d->own_stream);
-    for (auto& e : d->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
-    void* ptrs[] = {d->d_U, d->d_hdiag, d->d_ell_map, d->d_part, d->d_cidx, d->d_cval, d->d_ridx, d->d_rval, d->d_z, d->d_sigma,
-                    d->d_iters, d->d_status, d->d_dscratch, d->d_coef_c, d->d_coef_r, d->d_gr, d->d_ad, d->d_T,
-                    d->d_store_f, d->d_store_b, d->d_in_zc, d->d_in_wc, d->d_in_Er, d->d_in_wr, d->d_out_charge,
-                    d->d_out_cur, d->d_flags};
+    ws_destroy(d->ws);
+    void* ptrs[] = {d->d_U, d->d_hdiag, d->d_ell_map, d->d_cidx, d->d_cval, d->d_ridx, d->d_rval};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& ld : d->lead) {
@@ -815,9 +1088,40 @@ void negf_destroy(negf_device* d) {
         for (void* p : lp)
             if (p) (void)hipFree(p);
     }
-    if (d->h_flags) (void)hipHostFree(d->h_flags);
-    if (d->own_stream) (void)hipStreamDestroy(d->own_stream);
     delete d;
+}
+
+negf_status negf_workspace_create(negf_workspace** out, size_t store_bytes) {
+    if (!out) return fail(NEGF_EINVAL, "out is NULL");
+    *out = nullptr;
+    return ws_create(out, store_bytes);
+}
+
+void negf_workspace_destroy(negf_workspace* w) { ws_destroy(w); }
+
+negf_status negf_workspace_set_grid_scale(negf_workspace* w, int scale) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    if (scale < 1 || scale > 64) return fail(NEGF_EINVAL, "grid scale %d not in [1,64]", scale);
+    w->grid_scale = scale;
+    return NEGF_OK;
+}
+
+size_t negf_workspace_bytes(const negf_workspace* w) { return w ? w->bytes : 0; }
+
+negf_status negf_batch_solve_dev(negf_workspace* w, int n_jobs, const negf_job* jobs, void* hip_stream) {
+    TRY(check_batch(w, n_jobs, jobs, false));
+    return enqueue(w, n_jobs, jobs, (hipStream_t)hip_stream);
+}
+
+negf_status negf_batch_sync(negf_workspace* w, int* failed_job) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    HIPCHK(hipSetDevice(w->dev_id));
+    return finish(w, failed_job);
+}
+
+negf_status negf_batch_solve(negf_workspace* w, int n_jobs, const negf_job* jobs) {
+    TRY(check_batch(w, n_jobs, jobs, true));
+    return solve_host(w, n_jobs, jobs, nullptr);
 }
 
 }  // extern "C"

@@ -8,16 +8,25 @@
 // Cross-row data (pivot rows, right operands of block products) goes through
 // the group's slice of LDS.  Workgroups are a single wavefront.
 //
+// Batching.  A *job* is one device with its energy nodes (JobDesc).  A *unit*
+// is up to G consecutive nodes of one job handled by one wavefront, plus a
+// side (recursion direction or lead).  Kernels are persistent: each workgroup
+// pulls units from an atomic counter until the list is exhausted, so one
+// launch covers every job of a ring size, longest chains first.  A chain's
+// arithmetic never depends on which other chains share its wavefront, so a
+// job's results are bit-identical alone and in a batch.
+//
 // Kernels (see the host side for launch shapes):
-//   k_decimate   lead self-energies by Sancho-Rubio layer doubling, FP64
+//   k_decimate   lead self-energies by Sancho-Rubio layer doubling, FP64,
+//   k_decimate2  one-ring (k_decimate) and two-ring (k_decimate2) principal layers
 //   k_recur      left- and right-connected recursions (Algorithm 2), one chain
-//                per (energy, direction); stores y~/x~ (real axis) or y/x
+//                per (node, direction); stores y~/x~ (real axis) or y/x
 //                (contour) block by block
 //   k_cdiag      diag G^R_nn = (a_n - x_n - y_n)^{-1} at contour nodes,
-//                one item per (energy, ring)
+//                one item per (node, ring)
 //   k_column     lead block columns of G^R propagated with y~/x~ (Algorithm 1),
-//                diag(G Gamma G^H) per ring and T_LR, one chain per (energy, lead)
-//   k_coef / k_reduce / k_current   fixed-order FP64 energy sums (Eq. 4-5)
+//                diag(G Gamma G^H) per ring and T_LR, one chain per (node, lead)
+//   k_coef / k_reduce_* / k_current   fixed-order FP64 energy sums (Eq. 4-5)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -65,11 +74,11 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 template <typename T>
 __device__ __forceinline__ unsigned pivot_key(T re, T im, int r) {
     const float mag = (float)(fabs(re) + fabs(im));
-    return (__float_as_uint(mag) & 0xFFFFFFC0u) | (unsigned)(r + 32);
+    return (__float_as_uint(mag) & 0xFFFFFF80u) | (unsigned)(r + 64);
 }
 
 __device__ __forceinline__ int key_row(unsigned key, int B) {
-    const int p = (int)(key & 63u) - 32;
+    const int p = (int)(key & 127u) - 64;
     return p < 0 ? 0 : (p >= B ? B - 1 : p);
 }
 
@@ -77,7 +86,7 @@ __device__ __forceinline__ int key_row(unsigned key, int B) {
 // In-place Gauss-Jordan inversion with partial pivoting of the B x B matrix
 // whose row r sits in (ar, ai) of lane r.
 //  * Pivot of column k: the unused row of largest |re|+|im|, by an LDS max over
-//    keys packing the magnitude (float, top 26 bits) with the row (low 6 bits).
+//    keys packing the magnitude (float, top 25 bits) with the row (low 7 bits).
 //    The key of column k+1 is published while column k's update is still
 //    running (look-ahead), so the search costs no extra round trip.
 //  * Rows are never exchanged: the pivot row is relabelled, and the final
@@ -203,11 +212,9 @@ __device__ __forceinline__ void stage_row(const T (&xr)[B], const T (&xi)[B], cx
 }
 
 // ------------------------------------------------------------- arguments
-struct RgfArgs {
-    int N, b, n_c;            // rings, ring size, number of contour energies (first n_c)
-    int e0, ne;               // energies of this chunk: [e0, e0+ne)
-    int K;                    // ELL width of the ring couplings
-    int n_uniq;               // number of distinct coupling blocks
+struct JobDesc {
+    int N, n_c, n_r;          // rings, contour nodes (first n_c), real-axis nodes
+    int K, n_uniq;            // ELL width and number of distinct coupling blocks
     int hdiag_zero;           // 1 when every H_jj is zero (potential only)
     const double* U;          // [N*b]
     const cx<double>* hdiag;  // [N][b][b]
@@ -216,45 +223,82 @@ struct RgfArgs {
     const cx<double>* cval;   // [n_uniq][b][K]  H[cidx][j]
     const int* ridx;          // [n_uniq][b][K]  row-ELL: column index per (row j, t)
     const cx<double>* rval;   // [n_uniq][b][K]  H[j][ridx]
-    const cx<double>* z;      // [n_e] energy nodes (real nodes already carry i*eta)
-    const cx<double>* sigma;  // [n_e][2][b][b] lead self-energies (left, right)
-    void* store_f;            // [ne][N][b][b] cx<T>: slot n = y~_n (real) / y_n (contour); slot 0 = G_{N-1,N-1}
-    void* store_b;            // [ne][N][b][b] cx<T>: slot n = x~_n (real) / x_n (contour); slot N-1 = G_00
+    const cx<double>* z;      // [n_e] nodes (real nodes carry i*eta)
+    cx<double>* sigma;        // [n_e][2][b][b] lead self-energies (left, right)
     void* gr_diag;            // [n_c][N*b] cx<T>
     void* a_diag;             // [n_r][2][N*b] T
     double* Tout;             // [n_r]
+    int* iters;               // [n_e][2] decimation steps
+    int* status;              // [n_e]    |= 1 when a decimation did not converge
+    int period[2];            // lead principal-layer sizes
+    const cx<double>* D[2];   // [period][b][b] lead on-site blocks incl. lead potential
+    const cx<double>* V[2];   // h_up[0]
+    const cx<double>* VH[2];  // h_up[0]^H
+    const cx<double>* W[2];   // h_up[period-1]
+    const cx<double>* tau[2]; // H_{device edge, lead ring 0}
 };
 
-// a_n row r:  z delta - H_nn[r,:] - U[n b + r] delta - [n==0] Sigma_L[r,:] - [n==N-1] Sigma_R[r,:]
-template <typename T, int B>
-__device__ __forceinline__ void load_a_row(const RgfArgs& A, int e, int n, int r, bool act,
-                                           T (&xr)[B], T (&xi)[B]) {
-#pragma unroll
-    for (int j = 0; j < B; ++j) { xr[j] = T(0); xi[j] = T(0); }
-    if (!act) return;
-    const cx<double> z = A.z[e];
-    if (!A.hdiag_zero) {
-        const cx<double>* h = A.hdiag + ((size_t)n * B + r) * B;
-#pragma unroll
-        for (int j = 0; j < B; ++j) { xr[j] = T(-h[j].re); xi[j] = T(-h[j].im); }
+// A span: the nodes [e0, e0+cnt) of one job that one kernel launch covers
+// (all nodes, only the contour nodes or only the real-axis nodes of a chunk).
+// Its work is cut into units of G nodes (G (node, ring) items for k_cdiag),
+// each unit once per side (direction or lead).  Units are numbered span by
+// span: first[s] = units before span s, so unit w belongs to the span with
+// first[s] <= w < first[s+1], and within it side = local % sides.
+struct Span {
+    int job, e0, cnt, pad;
+    long long off;            // store element offset of node e0 (recursion stores)
+};
+
+struct Sched {
+    const JobDesc* jobs;
+    const Span* spans;
+    const int* first;         // [n_spans + 1] unit prefix
+    int n_spans;
+    int sides;                // sides per span: 2 (both directions / leads) or 1
+    int side0;                // first side (1 = backward direction / right lead alone)
+    int* counter;             // zero before launch
+    void* store_f;            // recursion stores: slot n = y~_n (real) / y_n (contour); slot 0 = G_{N-1,N-1}
+    void* store_b;            //                   slot n = x~_n (real) / x_n (contour); slot N-1 = G_00
+    cx<double>* scratch;      // decimation state, per workgroup: G chains x 6 b x b blocks
+    double tol;               // decimation tolerance
+    int maxit;                // decimation step limit
+};
+
+struct Unit {
+    int span, job, side, e0, cnt, i0;
+    long long off;
+};
+
+// next unit for this workgroup (one atomic per wavefront, uniform result); false when done
+template <int G>
+__device__ __forceinline__ bool next_unit(const Sched& S, Unit& u, bool items = false) {
+    int w = 0;
+    if (threadIdx.x == 0) w = atomicAdd(S.counter, 1);
+    w = __builtin_amdgcn_readfirstlane(w);
+    if (w >= S.first[S.n_spans]) return false;
+    int lo = 0, hi = S.n_spans;          // first[lo] <= w < first[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (S.first[mid] <= w) lo = mid; else hi = mid;
     }
-    // the diagonal term is formed in FP64 before rounding to T
-    double dre = z.re - A.U[(size_t)n * B + r];
-    double dim = z.im;
-#pragma unroll
-    for (int j = 0; j < B; ++j) {
-        if (j == r) { xr[j] += T(dre); xi[j] += T(dim); }
+    const Span sp = S.spans[lo];
+    const int local = w - S.first[lo];
+    u.span = lo;
+    u.job = sp.job;
+    u.side = S.side0 + local % S.sides;
+    const int blk = local / S.sides;
+    if (items) {                          // k_cdiag: G (node, ring) items
+        u.i0 = blk * G;
+        u.e0 = sp.e0;
+        u.off = sp.off;
+        u.cnt = 0;                        // set by the caller from N
+    } else {
+        u.e0 = sp.e0 + blk * G;
+        u.cnt = min(G, sp.e0 + sp.cnt - u.e0);
+        u.off = sp.off;
+        u.i0 = blk * G;                   // node offset of the unit inside the span
     }
-    if (n == 0) {
-        const cx<double>* s = A.sigma + ((size_t)e * 2 + 0) * B * B + (size_t)r * B;
-#pragma unroll
-        for (int j = 0; j < B; ++j) { xr[j] -= T(s[j].re); xi[j] -= T(s[j].im); }
-    }
-    if (n == A.N - 1) {
-        const cx<double>* s = A.sigma + ((size_t)e * 2 + 1) * B * B + (size_t)r * B;
-#pragma unroll
-        for (int j = 0; j < B; ++j) { xr[j] -= T(s[j].re); xi[j] -= T(s[j].im); }
-    }
+    return true;
 }
 
 // Writes the group's stage matrix to a store slot, coalesced: lane r writes
@@ -267,152 +311,156 @@ __device__ __forceinline__ void stage_to_global(const cx<T>* S, cx<T>* dst, int 
     }
 }
 
+// a_n row r into (xr, xi), optionally minus m:  z - H_nn - U_n - [n==0] Sigma_L - [n==N-1] Sigma_R
+template <typename T, int B>
+__device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r, double u, cx<double> z,
+                                          T (&xr)[B], T (&xi)[B]) {
+    if (!J.hdiag_zero) {
+        const cx<double>* h = J.hdiag + ((size_t)n * B + r) * B;
+#pragma unroll
+        for (int j = 0; j < B; ++j) { xr[j] -= T(h[j].re); xi[j] -= T(h[j].im); }
+    }
+    const T dre = T(z.re - u), dim = T(z.im);   // diagonal formed in FP64, then rounded
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+        if (j == r) { xr[j] += dre; xi[j] += dim; }
+    }
+    if (n == 0 || n == J.N - 1) {
+#pragma unroll
+        for (int lr = 0; lr < 2; ++lr) {
+            if ((lr == 0 && n == 0) || (lr == 1 && n == J.N - 1)) {
+                const cx<double>* sg = J.sigma + ((size_t)e * 2 + lr) * B * B + (size_t)r * B;
+#pragma unroll
+                for (int j = 0; j < B; ++j) { xr[j] -= T(sg[j].re); xi[j] -= T(sg[j].im); }
+            }
+        }
+    }
+}
+
 // ================================================================ k_recur ==
-// Chain = (energy, direction).  Direction 0 (forward) runs the left-connected
+// Chain = (node, direction).  Direction 0 (forward) runs the left-connected
 // recursion y_{n+1} = c_n (a_n - y_n)^{-1} b_n; direction 1 (backward) runs the
 // right-connected x_{n-1} = b_{n-1} (a_n - x_n)^{-1} c_{n-1}, with
 // b_n = -H_{n,n+1}, c_n = -H_{n+1,n} (Algorithm 2 in blocks of M).
-// Grid: [2 * ceil(ne / G)], first half forward; a workgroup never mixes directions.
-
 template <typename T, int B>
-__global__ __launch_bounds__(64, 2) void k_recur(RgfArgs A) {
+__global__ __launch_bounds__(64, 2) void k_recur(Sched S) {
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_prow[G][B];
     __shared__ unsigned s_keys[G][B];
+    extern __shared__ unsigned char s_dyn[];
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
-    const int half = gridDim.x / 2;
-    const int dir = blockIdx.x >= half ? 1 : 0;
-    const int wave = dir ? blockIdx.x - half : blockIdx.x;
-    const int el = wave * G + gi;
-    const bool act = (gi < G) && (el < A.ne);
     const int gsafe = gi < G ? gi : 0;
-    Grp<T, B> g{lane - gi * B, act, s_stage[gsafe], s_prow[gsafe], s_keys[gsafe]};
-    const int r = g.r;
-    const int e = A.e0 + (act ? el : 0);
-    const bool contour = e < A.n_c;
-    const int N = A.N, K = A.K;
-    cx<T>* store = reinterpret_cast<cx<T>*>(dir ? A.store_b : A.store_f) + (size_t)(act ? el : 0) * N * B * B;
+    const int r = lane - gi * B;
 
-    // coupling table (dynamic LDS): forward chains use the column-ELL, backward
-    // chains the row-ELL of the distinct coupling blocks
-    extern __shared__ unsigned char s_dyn[];
-    const int n_ell = A.n_uniq * B * K;
-    cx<T>* s_eval = reinterpret_cast<cx<T>*>(s_dyn);
-    unsigned char* s_eidx = s_dyn + (size_t)n_ell * sizeof(cx<T>);
-    {
-        const int* gidx = dir ? A.ridx : A.cidx;
-        const cx<double>* gval = dir ? A.rval : A.cval;
-        for (int q = lane; q < n_ell; q += 64) {
-            s_eidx[q] = (unsigned char)gidx[q];
-            const cx<double> v = gval[q];
-            s_eval[q] = cx<T>{T(v.re), T(v.im)};
+    Unit u;
+    while (next_unit<G>(S, u)) {
+        const JobDesc& J = S.jobs[u.job];
+        const int dir = u.side;
+        const bool act = (gi < G) && (gi < u.cnt);
+        Grp<T, B> g{r, act, s_stage[gsafe], s_prow[gsafe], s_keys[gsafe]};
+        const int e = u.e0 + (act ? gi : 0);
+        const bool contour = e < J.n_c;
+        const int N = J.N, K = J.K;
+        cx<T>* store = reinterpret_cast<cx<T>*>(dir ? S.store_b : S.store_f) + u.off +
+                       (size_t)(u.i0 + (act ? gi : 0)) * N * B * B;
+
+        // coupling table in LDS: forward chains use the column-ELL, backward the row-ELL
+        const int n_ell = J.n_uniq * B * K;
+        cx<T>* s_eval = reinterpret_cast<cx<T>*>(s_dyn);
+        unsigned char* s_eidx = s_dyn + (size_t)n_ell * sizeof(cx<T>);
+        wave_sync();
+        {
+            const int* gidx = dir ? J.ridx : J.cidx;
+            const cx<double>* gval = dir ? J.rval : J.cval;
+            for (int q = lane; q < n_ell; q += 64) {
+                s_eidx[q] = (unsigned char)gidx[q];
+                const cx<double> v = gval[q];
+                s_eval[q] = cx<T>{T(v.re), T(v.im)};
+            }
         }
-    }
-    wave_sync();
-    const cx<double> z = A.z[e];
-    double u_next = act ? A.U[(size_t)(dir ? N - 1 : 0) * B + r] : 0.0;
+        const cx<double> z = J.z[e];
+        double u_next = act ? J.U[(size_t)(dir ? N - 1 : 0) * B + r] : 0.0;
+        // the recursion state (y_n or x_n) is kept in the group's stage between steps
+        stage_row<T, B>(zero_row<T, B>(), zero_row<T, B>(), g.stage, r, act);
+        wave_sync();
 
-    // the recursion state (y_n or x_n) is kept in the group's stage between steps
-    stage_row<T, B>(zero_row<T, B>(), zero_row<T, B>(), g.stage, r, act);
-    wave_sync();
-
-    for (int s = 0; s < N; ++s) {
-        const int n = dir ? N - 1 - s : s;
-        const bool last = (s == N - 1);
-        if (last && __all(!act || contour)) break;
-        const double u = u_next;
-        if (!last && act) u_next = A.U[(size_t)(dir ? N - 2 - s : s + 1) * B + r];
-        // K = a_n - y_n, a_n = z - H_nn - U_n - [n==0] Sigma_L - [n==N-1] Sigma_R
-        T kr[B], ki[B];
+        for (int s = 0; s < N; ++s) {
+            const int n = dir ? N - 1 - s : s;
+            const bool last = (s == N - 1);
+            if (last && __all(!act || contour)) break;
+            const double uu = u_next;
+            if (!last && act) u_next = J.U[(size_t)(dir ? N - 2 - s : s + 1) * B + r];
+            T kr[B], ki[B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) { const cx<T> y = g.stage[r * B + j]; kr[j] = -y.re; ki[j] = -y.im; }
-        if (act) {
-            if (!A.hdiag_zero) {
-                const cx<double>* h = A.hdiag + ((size_t)n * B + r) * B;
-#pragma unroll
-                for (int j = 0; j < B; ++j) { kr[j] -= T(h[j].re); ki[j] -= T(h[j].im); }
+            for (int j = 0; j < B; ++j) { const cx<T> y = g.stage[r * B + j]; kr[j] = -y.re; ki[j] = -y.im; }
+            if (act) add_a_row<T, B>(J, e, n, r, uu, z, kr, ki);
+            gj_inverse<T, B>(kr, ki, g);   // (a_n - y_n)^{-1} -> stage
+            if (last) {
+                // G_{N-1,N-1} (forward) / G_00 (backward): exact, the other side is empty
+                if (!contour) stage_to_global<T, B>(g.stage, store + (size_t)(dir ? N - 1 : 0) * B * B, r, act);
+                break;
             }
-            const T dre = T(z.re - u), dim = T(z.im);   // diagonal formed in FP64, then rounded
+            const int c = dir ? N - 2 - s : s;   // coupling block index
+            const int slot = dir ? N - 2 - s : s + 1;
+            const int base = J.ell_map[c] * B * K;
+            // P product: t[r][j] = sum_l X[r][l] P[l][j]
+            //   fwd: P[l][j] = -H[l][j] (column-ELL);  bwd: P[l][j] = -conj(H[j][l]) (row-ELL)
+            T tr[B], ti[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) {
-                if (j == r) { kr[j] += dre; ki[j] += dim; }
-            }
-            if (n == 0 || n == N - 1) {
+            for (int j = 0; j < B; ++j) { tr[j] = T(0); ti[j] = T(0); }
+            if (act) {
+                for (int t = 0; t < K; ++t) {
 #pragma unroll
-                for (int lr = 0; lr < 2; ++lr) {
-                    if ((lr == 0 && n == 0) || (lr == 1 && n == N - 1)) {
-                        const cx<double>* sg = A.sigma + ((size_t)e * 2 + lr) * B * B + (size_t)r * B;
-#pragma unroll
-                        for (int j = 0; j < B; ++j) { kr[j] -= T(sg[j].re); ki[j] -= T(sg[j].im); }
+                    for (int j = 0; j < B; ++j) {
+                        const int q = base + j * K + t;
+                        const int l = s_eidx[q];
+                        const cx<T> h = s_eval[q];
+                        const T pr = -h.re, pi = dir ? h.im : -h.im;
+                        const cx<T> x = g.stage[r * B + l];
+                        tr[j] = fma(x.re, pr, fma(-x.im, pi, tr[j]));
+                        ti[j] = fma(x.re, pi, fma(x.im, pr, ti[j]));
                     }
                 }
             }
-        }
-        gj_inverse<T, B>(kr, ki, g);   // (a_n - y_n)^{-1} -> stage
-        if (last) {
-            // G_{N-1,N-1} (forward) / G_00 (backward): exact, the other side is empty
-            if (!contour) stage_to_global<T, B>(g.stage, store + (size_t)(dir ? N - 1 : 0) * B * B, r, act);
-            break;
-        }
-        const int c = dir ? N - 2 - s : s;   // coupling block index
-        const int slot = dir ? N - 2 - s : s + 1;
-        const int base = A.ell_map[c] * B * K;
-        // P product: t[r][j] = sum_l X[r][l] P[l][j]
-        //   fwd: P[l][j] = -H[l][j] (column-ELL);  bwd: P[l][j] = -conj(H[j][l]) (row-ELL)
-        T tr[B], ti[B];
+            wave_sync();
+            stage_row<T, B>(tr, ti, g.stage, r, act);
+            wave_sync();
+            if (!contour) stage_to_global<T, B>(g.stage, store + (size_t)slot * B * B, r, act);
+            // Q product: y[r][:] = sum_l Q[r][l] t[l][:]
+            //   fwd: Q[r][l] = -conj(H[l][r]) (column-ELL of column r);  bwd: Q[r][l] = -H[r][l] (row-ELL)
+            T yr[B], yi[B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) { tr[j] = T(0); ti[j] = T(0); }
-        if (act) {
-            for (int t = 0; t < K; ++t) {
-#pragma unroll
-                for (int j = 0; j < B; ++j) {
-                    const int q = base + j * K + t;
+            for (int j = 0; j < B; ++j) { yr[j] = T(0); yi[j] = T(0); }
+            if (act) {
+                for (int t = 0; t < K; ++t) {
+                    const int q = base + r * K + t;
                     const int l = s_eidx[q];
                     const cx<T> h = s_eval[q];
-                    const T pr = -h.re, pi = dir ? h.im : -h.im;
-                    const cx<T> x = g.stage[r * B + l];
-                    tr[j] = fma(x.re, pr, fma(-x.im, pi, tr[j]));
-                    ti[j] = fma(x.re, pi, fma(x.im, pr, ti[j]));
+                    const T qr = -h.re, qi = dir ? -h.im : h.im;
+#pragma unroll
+                    for (int j = 0; j < B; ++j) {
+                        const cx<T> x = g.stage[l * B + j];
+                        yr[j] = fma(qr, x.re, fma(-qi, x.im, yr[j]));
+                        yi[j] = fma(qr, x.im, fma(qi, x.re, yi[j]));
+                    }
                 }
             }
+            wave_sync();
+            stage_row<T, B>(yr, yi, g.stage, r, act);
+            wave_sync();
+            if (contour) stage_to_global<T, B>(g.stage, store + (size_t)slot * B * B, r, act);
         }
         wave_sync();
-        stage_row<T, B>(tr, ti, g.stage, r, act);
-        wave_sync();
-        if (!contour) stage_to_global<T, B>(g.stage, store + (size_t)slot * B * B, r, act);
-        // Q product: y[r][:] = sum_l Q[r][l] t[l][:]
-        //   fwd: Q[r][l] = -conj(H[l][r]) (column-ELL of column r);  bwd: Q[r][l] = -H[r][l] (row-ELL)
-        T yr[B], yi[B];
-#pragma unroll
-        for (int j = 0; j < B; ++j) { yr[j] = T(0); yi[j] = T(0); }
-        if (act) {
-            for (int t = 0; t < K; ++t) {
-                const int q = base + r * K + t;
-                const int l = s_eidx[q];
-                const cx<T> h = s_eval[q];
-                const T qr = -h.re, qi = dir ? -h.im : h.im;
-#pragma unroll
-                for (int j = 0; j < B; ++j) {
-                    const cx<T> x = g.stage[l * B + j];
-                    yr[j] = fma(qr, x.re, fma(-qi, x.im, yr[j]));
-                    yi[j] = fma(qr, x.im, fma(qi, x.re, yi[j]));
-                }
-            }
-        }
-        wave_sync();
-        stage_row<T, B>(yr, yi, g.stage, r, act);
-        wave_sync();
-        if (contour) stage_to_global<T, B>(g.stage, store + (size_t)slot * B * B, r, act);
     }
 }
 
 // ================================================================ k_cdiag ==
-// Item = (contour energy, ring n): G_nn = (a_n - x_n - y_n)^{-1}, diagonal kept.
+// Item = (contour node, ring n): G_nn = (a_n - x_n - y_n)^{-1}, diagonal kept.
 template <typename T, int B>
-__global__ __launch_bounds__(64, 2) void k_cdiag(RgfArgs A, int nc_chunk) {
+__global__ __launch_bounds__(64, 2) void k_cdiag(Sched S) {
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_prow[G][B];
@@ -420,177 +468,179 @@ __global__ __launch_bounds__(64, 2) void k_cdiag(RgfArgs A, int nc_chunk) {
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
-    const int item = blockIdx.x * G + gi;
-    const int N = A.N;
-    const bool act = (gi < G) && (item < nc_chunk * N);
     const int gsafe = gi < G ? gi : 0;
-    Grp<T, B> g{lane - gi * B, act, s_stage[gsafe], s_prow[gsafe], s_keys[gsafe]};
-    const int r = g.r;
-    const int el = act ? item / N : 0;
-    const int n = act ? item - el * N : 0;
-    const int e = A.e0 + el;
+    const int r = lane - gi * B;
 
-    T kr[B], ki[B];
-    load_a_row<T, B>(A, e, n, r, act, kr, ki);
-    if (act) {
-        const cx<T>* sf = reinterpret_cast<const cx<T>*>(A.store_f) + ((size_t)el * N + n) * B * B + (size_t)r * B;
-        const cx<T>* sb = reinterpret_cast<const cx<T>*>(A.store_b) + ((size_t)el * N + n) * B * B + (size_t)r * B;
-        if (n > 0) {
+    Unit u;
+    while (next_unit<G>(S, u, true)) {
+        const JobDesc& J = S.jobs[u.job];
+        const int N = J.N;
+        const int n_items = S.spans[u.span].cnt * N;
+        const bool act = (gi < G) && (u.i0 + gi < n_items);
+        Grp<T, B> g{r, act, s_stage[gsafe], s_prow[gsafe], s_keys[gsafe]};
+        const int item = u.i0 + (act ? gi : 0);
+        const int el = item / N;                 // node inside the span
+        const int e = u.e0 + el;                 // node inside the job
+        const int n = item - el * N;
+
+        T kr[B], ki[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<T> v = sf[j]; kr[j] -= v.re; ki[j] -= v.im; }
-        }
-        if (n < N - 1) {
+        for (int j = 0; j < B; ++j) { kr[j] = T(0); ki[j] = T(0); }
+        if (act) {
+            const size_t o = u.off + ((size_t)el * N + n) * B * B + (size_t)r * B;
+            const cx<T>* sf = reinterpret_cast<const cx<T>*>(S.store_f) + o;
+            const cx<T>* sb = reinterpret_cast<const cx<T>*>(S.store_b) + o;
+            if (n > 0) {
 #pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<T> v = sb[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                for (int j = 0; j < B; ++j) { const cx<T> v = sf[j]; kr[j] -= v.re; ki[j] -= v.im; }
+            }
+            if (n < N - 1) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) { const cx<T> v = sb[j]; kr[j] -= v.re; ki[j] -= v.im; }
+            }
+            add_a_row<T, B>(J, e, n, r, J.U[(size_t)n * B + r], J.z[e], kr, ki);
         }
-    }
-    gj_inverse<T, B>(kr, ki, g);
-    if (act) {
-        const cx<T> d = g.stage[r * B + r];
-        reinterpret_cast<cx<T>*>(A.gr_diag)[(size_t)e * N * B + (size_t)n * B + r] = d;
+        gj_inverse<T, B>(kr, ki, g);
+        if (act) {
+            const cx<T> d = g.stage[r * B + r];
+            reinterpret_cast<cx<T>*>(J.gr_diag)[(size_t)e * N * B + (size_t)n * B + r] = d;
+        }
+        wave_sync();
     }
 }
 
 // =============================================================== k_column ==
-// Chain = (real energy, lead).  Right lead: W_n = G_{n,N-1}, W_{N-1} from the
+// Chain = (real node, lead).  Right lead: W_n = G_{n,N-1}, W_{N-1} from the
 // forward store, W_{n-1} = -y~_n W_n.  Left lead: W_n = G_{n,0}, W_0 from the
-// backward store, W_{n+1} = -x~_n W_n (Algorithm 1, lines 3-4 and 6-8).
+// backward store, W_{n+1} = -x~_n W_n (the off-diagonal column recursions of Algorithm 1).
 // Each ring's diag(W Gamma W^H) is written; the right chain ends with
 // T_LR = Tr[Gamma_L W_0 Gamma_R W_0^H] (Eq. 5).
-// Grid: [2 * ceil(nr_chunk / G)], first half left lead.
-template <typename T, typename TS, int B>
-__global__ __launch_bounds__(64, 2) void k_column(RgfArgs A, int er0, int nr_chunk) {
+template <typename T, int B>
+__global__ __launch_bounds__(64, 2) void k_column(Sched S) {
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_gam[G][B * B];
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
-    const int half = gridDim.x / 2;
-    const int lead = blockIdx.x >= half ? 1 : 0;
-    const int wave = lead ? blockIdx.x - half : blockIdx.x;
-    const int k = wave * G + gi;                 // real energy within the chunk's real part
-    const bool act = (gi < G) && (k < nr_chunk);
     const int gsafe = gi < G ? gi : 0;
     const int r = lane - gi * B;
-    cx<T>* S = s_stage[gsafe];
+    cx<T>* St = s_stage[gsafe];
     cx<T>* Gm = s_gam[gsafe];
-    const int N = A.N;
-    const int e = er0 + (act ? k : 0);          // global energy index (>= n_c)
-    const int el = e - A.e0;                    // index inside the chunk's store
-    const int ir = e - A.n_c;                   // real-axis index
 
-    // Gamma of this chain's lead, FP64 -> T
-    if (act) {
-        const cx<double>* s = A.sigma + ((size_t)e * 2 + lead) * B * B;
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-            const cx<double> a = s[r * B + j], b = s[j * B + r];
-            // Gamma[r][j] = i (Sigma[r][j] - conj(Sigma[j][r]))
-            Gm[r * B + j] = cx<T>{T(-(a.im + b.im)), T(a.re - b.re)};
-        }
-    }
-    const cx<TS>* store = reinterpret_cast<const cx<TS>*>(lead ? A.store_f : A.store_b) + (size_t)(act ? el : 0) * N * B * B;
-    T wr[B], wi[B];
-#pragma unroll
-    for (int j = 0; j < B; ++j) { wr[j] = T(0); wi[j] = T(0); }
-    if (act) {
-        const cx<TS>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
-#pragma unroll
-        for (int j = 0; j < B; ++j) { const cx<TS> v = w0[j]; wr[j] = T(v.re); wi[j] = T(v.im); }
-    }
-    stage_row<T, B>(wr, wi, S, r, act);
-    wave_sync();
-    T* aout = reinterpret_cast<T*>(A.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
-
-    T vr[B], vi[B];
-    for (int s = 0; s < N; ++s) {
-        const int n = lead ? N - 1 - s : s;
-        // propagator row for this step, loaded ahead of the Gamma product
-        T pr[B], pi[B];
-#pragma unroll
-        for (int j = 0; j < B; ++j) { pr[j] = T(0); pi[j] = T(0); }
-        if (act && s < N - 1) {
-            const cx<TS>* p = store + ((size_t)n * B + r) * B;
-#pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<TS> v = p[j]; pr[j] = -T(v.re); pi[j] = -T(v.im); }
-        }
-        // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j])
-        row_mul<T, B>(wr, wi, Gm, vr, vi);
-        if (act) {
-            T acc = T(0);
-#pragma unroll
-            for (int j = 0; j < B; ++j) acc = fma(vr[j], wr[j], fma(vi[j], wi[j], acc));
-            aout[(size_t)n * B + r] = acc;
-        }
-        if (s == N - 1) break;
-        // W_next[r][:] = -sum_k P[r][k] W[k][:],  P = y~_n (right) or x~_n (left)
-        row_mul<T, B>(pr, pi, S, wr, wi);
+    Unit u;
+    while (next_unit<G>(S, u)) {
+        const JobDesc& J = S.jobs[u.job];
+        const int lead = u.side;
+        const bool act = (gi < G) && (gi < u.cnt);
+        const int N = J.N;
+        const int e = u.e0 + (act ? gi : 0);     // node index within the job (>= n_c)
+        const int ir = e - J.n_c;                 // real-axis index
         wave_sync();
-        stage_row<T, B>(wr, wi, S, r, act);
-        wave_sync();
-    }
-    if (lead == 1) {
-        // W = G_{0,N-1} (in S and registers), v = W Gamma_R (registers).
-        // T_LR = sum_{r,j'} Gamma_L[j'][r] (W Gamma_R W^H)[r][j']
-        double t = 0.0;
         if (act) {
-            const cx<double>* sl = A.sigma + ((size_t)e * 2 + 0) * B * B;
-            for (int jp = 0; jp < B; ++jp) {
-                double mr = 0.0, mi = 0.0;   // (W Gamma_R W^H)[r][jp] = sum_j v[j] conj(W[jp][j])
+            const cx<double>* s = J.sigma + ((size_t)e * 2 + lead) * B * B;
 #pragma unroll
-                for (int j = 0; j < B; ++j) {
-                    const cx<T> w = S[jp * B + j];
-                    mr += (double)vr[j] * (double)w.re + (double)vi[j] * (double)w.im;
-                    mi += (double)vi[j] * (double)w.re - (double)vr[j] * (double)w.im;
-                }
-                const cx<double> a = sl[jp * B + r], b = sl[r * B + jp];
-                const double gre = -(a.im + b.im), gim = a.re - b.re;   // Gamma_L[jp][r]
-                t += gre * mr - gim * mi;
+            for (int j = 0; j < B; ++j) {
+                const cx<double> a = s[r * B + j], b = s[j * B + r];
+                // Gamma[r][j] = i (Sigma[r][j] - conj(Sigma[j][r]))
+                Gm[r * B + j] = cx<T>{T(-(a.im + b.im)), T(a.re - b.re)};
             }
         }
-        // group sum in fixed order through LDS (reuse Gm: everyone is done with it)
-        wave_sync();
-        double* red = reinterpret_cast<double*>(Gm);
-        if (act) red[r] = t;
-        wave_sync();
-        if (act && r == 0) {
-            double sum = 0.0;
-            for (int q = 0; q < B; ++q) sum += red[q];
-            A.Tout[ir] = sum;
+        const cx<T>* store = reinterpret_cast<const cx<T>*>(lead ? S.store_f : S.store_b) + u.off +
+                             (size_t)(u.i0 + (act ? gi : 0)) * N * B * B;
+        T wr[B], wi[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) { wr[j] = T(0); wi[j] = T(0); }
+        if (act) {
+            const cx<T>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
+#pragma unroll
+            for (int j = 0; j < B; ++j) { const cx<T> v = w0[j]; wr[j] = v.re; wi[j] = v.im; }
         }
+        stage_row<T, B>(wr, wi, St, r, act);
+        wave_sync();
+        T* aout = reinterpret_cast<T*>(J.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
+
+        T vr[B], vi[B];
+        for (int s = 0; s < N; ++s) {
+            const int n = lead ? N - 1 - s : s;
+            // propagator row for this step, loaded ahead of the Gamma product
+            T pr[B], pi[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) { pr[j] = T(0); pi[j] = T(0); }
+            if (act && s < N - 1) {
+                const cx<T>* p = store + ((size_t)n * B + r) * B;
+#pragma unroll
+                for (int j = 0; j < B; ++j) { const cx<T> v = p[j]; pr[j] = -v.re; pi[j] = -v.im; }
+            }
+            // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j])
+            row_mul<T, B>(wr, wi, Gm, vr, vi);
+            if (act) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc = fma(vr[j], wr[j], fma(vi[j], wi[j], acc));
+                aout[(size_t)n * B + r] = acc;
+            }
+            if (s == N - 1) break;
+            // W_next[r][:] = -sum_k P[r][k] W[k][:],  P = y~_n (right) or x~_n (left)
+            row_mul<T, B>(pr, pi, St, wr, wi);
+            wave_sync();
+            stage_row<T, B>(wr, wi, St, r, act);
+            wave_sync();
+        }
+        if (lead == 1) {
+            // W = G_{0,N-1} (in St and registers), v = W Gamma_R (registers).
+            // T_LR = sum_{r,j'} Gamma_L[j'][r] (W Gamma_R W^H)[r][j']
+            double t = 0.0;
+            if (act) {
+                const cx<double>* sl = J.sigma + ((size_t)e * 2 + 0) * B * B;
+                for (int jp = 0; jp < B; ++jp) {
+                    double mr = 0.0, mi = 0.0;   // (W Gamma_R W^H)[r][jp] = sum_j v[j] conj(W[jp][j])
+#pragma unroll
+                    for (int j = 0; j < B; ++j) {
+                        const cx<T> wv = St[jp * B + j];
+                        mr += (double)vr[j] * (double)wv.re + (double)vi[j] * (double)wv.im;
+                        mi += (double)vi[j] * (double)wv.re - (double)vr[j] * (double)wv.im;
+                    }
+                    const cx<double> a = sl[jp * B + r], b = sl[r * B + jp];
+                    const double gre = -(a.im + b.im), gim = a.re - b.re;   // Gamma_L[jp][r]
+                    t += gre * mr - gim * mi;
+                }
+            }
+            // group sum in fixed order through LDS (Gm is free now)
+            wave_sync();
+            double* red = reinterpret_cast<double*>(Gm);
+            if (act) red[r] = t;
+            wave_sync();
+            if (act && r == 0) {
+                double sum = 0.0;
+                for (int q = 0; q < B; ++q) sum += red[q];
+                J.Tout[ir] = sum;
+            }
+        }
+        wave_sync();
     }
 }
 
 // ============================================================= k_decimate ==
-// Chain = (energy, lead).  Sancho-Rubio layer doubling written on the ring
-// blocks of a principal layer of `period` rings.  For a nearest-ring lead the
-// doubling keeps alpha (beta) non-zero only in its (P-1,0) ((0,P-1)) block and
-// changes only the corner diagonal blocks of eps, so every product is b x b:
-//   P = 1:  g = (z-e)^{-1}; es += A g Bm; e += A g Bm + Bm g A; A <- A g A; Bm <- Bm g Bm
-//   P = 2:  eps = [[e00, V],[V^H, e11]], eps_s(1,1) == e11, eps_s(0,0) = D0;
-//           g00 = (z-e00 - V (z-e11)^{-1} V^H)^{-1},  g11 = (z-e11 - V^H (z-e00)^{-1} V)^{-1}
-//           g01 = g00 V (z-e11)^{-1},  g10 = g11 V^H (z-e00)^{-1}
-//           e11 += A g00 Bm;  e00 += Bm g11 A;  A <- A g01 A;  Bm <- Bm g10 Bm
-// until every |A_ij|, |Bm_ij| < tol.  Then Sigma = tau g_s[0,0] tau^H.
-// Chain state lives in a global scratch (each lane touches only its own rows);
-// right operands are staged in three LDS matrices per group.
-struct DecArgs {
-    int b, n, maxit;             // n energies
-    double tol;
-    int lead_only;               // -1: both leads (grid = 2 halves); 0/1: that lead only
-    int period[2];               // per lead: 1 or 2
-    const cx<double>* z;         // [n] nodes, used as given
-    const cx<double>* D[2];      // [period][b][b] lead on-site blocks incl. lead potential
-    const cx<double>* V[2];      // [b][b]  h_up[0] (period 2: intra-cell coupling)
-    const cx<double>* VH[2];     // [b][b]  V^H
-    const cx<double>* W[2];      // [b][b]  h_up[period-1] (inter-cell coupling)
-    const cx<double>* tau[2];    // [b][b]
-    cx<double>* scratch;         // [2][n][6][b][b]
-    cx<double>* sigma;           // [n][2][b][b]  written at [k][lead]
-    int* iters;                  // [n][2]
-    int* status;                 // [n]  |= 1 on non-convergence
-};
+// Chain = (energy, lead).  Sancho-Rubio layer doubling on the principal layer
+// of `period` rings (Section 2.2.2).  The coupling of a layer to the next, alpha,
+// is non-zero only in its (P-1,0) block A, and beta = alpha^H only in its
+// (0,P-1) block Bm; the doubling keeps that shape and changes only the corner
+// diagonal blocks of eps, so every product is b x b.  Convergence: every
+// |A_ij|, |Bm_ij| < tol.  Then Sigma = tau g_s[0,0] tau^H.  Nodes are used as
+// given (real nodes carry i*eta).
+//
+//   P = 1 (k_decimate):  g = (z-e)^{-1}; es += A g Bm; e += A g Bm + Bm g A;
+//                        A <- A g A; Bm <- Bm g Bm;  g_s = (z-es)^{-1}
+//   P = 2 (k_decimate2): eps = [[e00, V],[V^H, e11]], eps_s(0,0) = D0,
+//                        eps_s(0,1) = V and eps_s(1,1) == e11 at every step;
+//                        g = (z-eps)^{-1} by one pivoted 2b x 2b inversion;
+//                        e11 += A g00 Bm; e00 += Bm g11 A; A <- A g01 A;
+//                        Bm <- Bm g10 Bm;  g_s00 = [(z-eps_s)^{-1}]_00.
+// The 2b x 2b inversion matters: forming g00 from the Schur complement
+// z-e00 - V (z-e11)^{-1} V^H loses about |V|^2 |(z-e11)^{-1}| / |g00^{-1}| of
+// the working precision, which is total where z meets an eigenvalue of a single
+// ring block (E = 0 for zigzag rings with zero on-site energy).
 
 template <int B>
 __device__ __forceinline__ void gl_row(const cx<double>* M, int r, double (&xr)[B], double (&xi)[B]) {
@@ -603,58 +653,80 @@ __device__ __forceinline__ void gs_row(cx<double>* M, int r, const double (&xr)[
     for (int j = 0; j < B; ++j) M[r * B + j] = cx<double>{xr[j], xi[j]};
 }
 
+// out = x * Y for a B x B block Y inside an LDS matrix of row stride LD
+template <int B, int LD>
+__device__ __forceinline__ void row_mul_ld(const double (&xr)[B], const double (&xi)[B], const cx<double>* Y,
+                                           double (&orr)[B], double (&oi)[B]) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) { orr[j] = 0.0; oi[j] = 0.0; }
+#pragma unroll 1
+    for (int k = 0; k < B; ++k) {
+        const double a = xr[k], b = xi[k];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const cx<double> q = Y[k * LD + j];
+            orr[j] = fma(a, q.re, fma(-b, q.im, orr[j]));
+            oi[j] = fma(a, q.im, fma(b, q.re, oi[j]));
+        }
+    }
+}
+
+// Sigma row r = (tau[r,:] g) tau^H, g = B x B block of row stride LD in LDS
+template <int B, int LD>
+__device__ __forceinline__ void sigma_row(const cx<double>* tau, const cx<double>* g, int r, cx<double>* out) {
+    double xr[B], xi[B], ur[B], ui[B], dr[B], di[B];
+    gl_row<B>(tau, r, xr, xi);
+    row_mul_ld<B, LD>(xr, xi, g, ur, ui);
+#pragma unroll
+    for (int j = 0; j < B; ++j) { dr[j] = 0.0; di[j] = 0.0; }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const cx<double> h = tau[j * B + q];   // tau^H[q][j] = conj(tau[j][q])
+            dr[j] += ur[q] * h.re + ui[q] * h.im;
+            di[j] += ui[q] * h.re - ur[q] * h.im;
+        }
+    }
+    gs_row<B>(out, r, dr, di);
+}
+
+// ---- P = 1: group of B lanes per chain, state in a per-workgroup global scratch
 template <int B>
-__global__ __launch_bounds__(64) void k_decimate(DecArgs Dg) {
+__device__ __forceinline__ void decimate_chain1(const JobDesc& J, int lead, double tol, int maxit, int k, bool act,
+                                                cx<double>* sc, cx<double> (&s_buf)[3][64 / B][B * B],
+                                                cx<double> (&s_prow)[64 / B][B], unsigned (&s_keys)[64 / B][B],
+                                                int (&s_flag)[64 / B]) {
     constexpr int G = 64 / B;
     using T = double;
-    __shared__ cx<T> s_buf[3][G][B * B];
-    __shared__ cx<T> s_prow[G][B];
-    __shared__ unsigned s_keys[G][B];
-    __shared__ int s_flag[G];
-
     const int lane = threadIdx.x;
     const int gi = lane / B;
-    const int half = gridDim.x / 2;
-    const int lead = Dg.lead_only >= 0 ? Dg.lead_only : (blockIdx.x >= half ? 1 : 0);
-    const int wave = (Dg.lead_only < 0 && lead == 1) ? blockIdx.x - half : blockIdx.x;
-    const int k = wave * G + gi;
-    const bool act = (gi < G) && (k < Dg.n);
-    struct {
-        int period, maxit, lead;
-        double tol;
-        const cx<double> *D, *V, *VH, *W, *tau;
-    } D{Dg.period[lead], Dg.maxit, lead, Dg.tol, Dg.D[lead], Dg.V[lead], Dg.VH[lead], Dg.W[lead], Dg.tau[lead]};
     const int gsafe = gi < G ? gi : 0;
     const int r = lane - gi * B;
     cx<T>* L0 = s_buf[0][gsafe];
     cx<T>* L1 = s_buf[1][gsafe];
     cx<T>* L2 = s_buf[2][gsafe];
-    const int kk = act ? k : 0;
-    const cx<double> z = Dg.z[kk];
-    cx<double>* sc = Dg.scratch + ((size_t)lead * Dg.n + kk) * 6 * B * B;
-    cx<double>* E0 = sc;               // e00 (P=2) or e (P=1)
-    cx<double>* E1 = sc + 1 * B * B;   // e11 == eps_s(1,1) (P=2) or eps_s (P=1)
-    cx<double>* MA = sc + 2 * B * B;   // alpha corner block
-    cx<double>* MB = sc + 3 * B * B;   // beta corner block
-    cx<double>* X1 = sc + 4 * B * B;   // g01
-    cx<double>* X2 = sc + 5 * B * B;   // g10
+    const cx<double> z = J.z[k];
+    cx<double>* E0 = sc;               // e
+    cx<double>* E1 = sc + 1 * B * B;   // eps_s
+    cx<double>* MA = sc + 2 * B * B;   // alpha
+    cx<double>* MB = sc + 3 * B * B;   // beta
 
     bool live = act;   // chain still iterating
     T xr[B], xi[B], ur[B], ui[B], dr[B], di[B], nr[B], ni[B];
     if (act) {
-        gl_row<B>(D.D, r, xr, xi);
+        gl_row<B>(J.D[lead], r, xr, xi);
         gs_row<B>(E0, r, xr, xi);
-        if (D.period == 2) gl_row<B>(D.D + B * B, r, xr, xi);
         gs_row<B>(E1, r, xr, xi);
-        gl_row<B>(D.W, r, xr, xi);
+        gl_row<B>(J.W[lead], r, xr, xi);
         gs_row<B>(MA, r, xr, xi);
 #pragma unroll
-        for (int j = 0; j < B; ++j) { const cx<double> v = D.W[j * B + r]; xr[j] = v.re; xi[j] = -v.im; }
+        for (int j = 0; j < B; ++j) { const cx<double> v = J.W[lead][j * B + r]; xr[j] = v.re; xi[j] = -v.im; }
         gs_row<B>(MB, r, xr, xi);
     }
 
-    // dst <- (z I - M[r,:] - [sub_u] u)^{-1} for the live chains
-    auto inv_from = [&](const cx<double>* M, bool sub_u, cx<T>* dst) {
+    // dst <- (z I - M)^{-1} for the live chains
+    auto inv_from = [&](const cx<double>* M, cx<T>* dst) {
         T kr[B], ki[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) { kr[j] = T(0); ki[j] = T(0); }
@@ -662,8 +734,8 @@ __global__ __launch_bounds__(64) void k_decimate(DecArgs Dg) {
             gl_row<B>(M, r, kr, ki);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
-                kr[j] = -kr[j] - (sub_u ? ur[j] : T(0));
-                ki[j] = -ki[j] - (sub_u ? ui[j] : T(0));
+                kr[j] = -kr[j];
+                ki[j] = -ki[j];
                 if (j == r) { kr[j] += z.re; ki[j] += z.im; }
             }
         }
@@ -672,24 +744,6 @@ __global__ __launch_bounds__(64) void k_decimate(DecArgs Dg) {
     };
     auto stage_global = [&](const cx<double>* M, cx<T>* dst) {
         if (live) { T a[B], b[B]; gl_row<B>(M, r, a, b); stage_row<T, B>(a, b, dst, r, true); }
-    };
-    // u <- u * M where M (global, uniform across lanes of the wave) is B x B
-    auto mul_uniform = [&](const cx<double>* M) {
-        if (live) {
-#pragma unroll
-            for (int j = 0; j < B; ++j) { dr[j] = T(0); di[j] = T(0); }
-#pragma unroll
-            for (int q = 0; q < B; ++q) {
-#pragma unroll
-                for (int j = 0; j < B; ++j) {
-                    const cx<double> h = M[q * B + j];
-                    dr[j] += ur[q] * h.re - ui[q] * h.im;
-                    di[j] += ur[q] * h.im + ui[q] * h.re;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < B; ++j) { ur[j] = dr[j]; ui[j] = di[j]; }
-        }
     };
     auto add_global = [&](cx<double>* M, const T (&ar)[B], const T (&ai)[B]) {
         if (live) {
@@ -701,78 +755,26 @@ __global__ __launch_bounds__(64) void k_decimate(DecArgs Dg) {
         }
     };
 
-    int it_done = D.maxit;
-    for (int it = 1; it <= D.maxit; ++it) {
-        if (D.period == 1) {
-            inv_from(E0, false, L0);                      // L0 = g
-            stage_global(MB, L1);
-            stage_global(MA, L2);
-            wave_sync();
-            if (live) gl_row<B>(MA, r, xr, xi);
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // A g
-            row_mul<T, B>(ur, ui, L1, dr, di);            // A g Bm
-            row_mul<T, B>(ur, ui, L2, nr, ni);            // A g A
-            add_global(E1, dr, di);                       // eps_s += A g Bm
-            if (live) { gs_row<B>(MA, r, nr, ni); gl_row<B>(MB, r, xr, xi); }
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // Bm g
-            row_mul<T, B>(ur, ui, L2, nr, ni);            // Bm g A
+    int it_done = maxit;
+    for (int it = 1; it <= maxit; ++it) {
+        inv_from(E0, L0);                             // L0 = g
+        stage_global(MB, L1);
+        stage_global(MA, L2);
+        wave_sync();
+        if (live) gl_row<B>(MA, r, xr, xi);
+        row_mul<T, B>(xr, xi, L0, ur, ui);            // A g
+        row_mul<T, B>(ur, ui, L1, dr, di);            // A g Bm
+        row_mul<T, B>(ur, ui, L2, nr, ni);            // A g A
+        add_global(E1, dr, di);                       // eps_s += A g Bm
+        if (live) { gs_row<B>(MA, r, nr, ni); gl_row<B>(MB, r, xr, xi); }
+        row_mul<T, B>(xr, xi, L0, ur, ui);            // Bm g
+        row_mul<T, B>(ur, ui, L2, nr, ni);            // Bm g A
 #pragma unroll
-            for (int j = 0; j < B; ++j) { nr[j] += dr[j]; ni[j] += di[j]; }
-            add_global(E0, nr, ni);                       // eps += A g Bm + Bm g A
-            row_mul<T, B>(ur, ui, L1, nr, ni);            // Bm g Bm
-            if (live) gs_row<B>(MB, r, nr, ni);
-            wave_sync();
-        } else {
-            inv_from(E1, false, L0);                      // L0 = (z - e11)^{-1}
-            if (live) gl_row<B>(D.V, r, xr, xi);
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // R1 = V (z - e11)^{-1}
-            stage_row<T, B>(ur, ui, L1, r, live);         // L1 = R1
-            mul_uniform(D.VH);                            // u = R1 V^H
-            wave_sync();
-            inv_from(E0, true, L2);                       // L2 = g00
-            lds_row_mul<T, B>(L2, r, L1, dr, di);         // g01 = g00 R1
-            if (live) gs_row<B>(X1, r, dr, di);
-            wave_sync();
-            inv_from(E0, false, L0);                      // L0 = (z - e00)^{-1}
-            if (live) gl_row<B>(D.VH, r, xr, xi);
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // Q = V^H (z - e00)^{-1}
-            wave_sync();
-            stage_row<T, B>(ur, ui, L1, r, live);         // L1 = Q
-            mul_uniform(D.V);                             // u = Q V
-            wave_sync();
-            inv_from(E1, true, L0);                       // L0 = g11
-            lds_row_mul<T, B>(L0, r, L1, dr, di);         // g10 = g11 Q
-            if (live) gs_row<B>(X2, r, dr, di);
-            wave_sync();
-            stage_global(MB, L1);                         // L1 = Bm
-            wave_sync();
-            if (live) gl_row<B>(MA, r, xr, xi);
-            row_mul<T, B>(xr, xi, L2, ur, ui);            // A g00
-            row_mul<T, B>(ur, ui, L1, dr, di);            // A g00 Bm
-            add_global(E1, dr, di);
-            wave_sync();
-            stage_global(MA, L2);                         // L2 = A
-            wave_sync();
-            if (live) gl_row<B>(MB, r, xr, xi);
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // Bm g11
-            row_mul<T, B>(ur, ui, L2, dr, di);            // Bm g11 A
-            add_global(E0, dr, di);
-            wave_sync();
-            stage_global(X1, L0);                         // L0 = g01
-            wave_sync();
-            if (live) gl_row<B>(MA, r, xr, xi);
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // A g01
-            row_mul<T, B>(ur, ui, L2, dr, di);            // A g01 A
-            if (live) gs_row<B>(MA, r, dr, di);
-            wave_sync();
-            stage_global(X2, L0);                         // L0 = g10
-            wave_sync();
-            if (live) gl_row<B>(MB, r, xr, xi);
-            row_mul<T, B>(xr, xi, L0, ur, ui);            // Bm g10
-            row_mul<T, B>(ur, ui, L1, dr, di);            // Bm g10 Bm
-            if (live) gs_row<B>(MB, r, dr, di);
-            wave_sync();
-        }
+        for (int j = 0; j < B; ++j) { nr[j] += dr[j]; ni[j] += di[j]; }
+        add_global(E0, nr, ni);                       // eps += A g Bm + Bm g A
+        row_mul<T, B>(ur, ui, L1, nr, ni);            // Bm g Bm
+        if (live) gs_row<B>(MB, r, nr, ni);
+        wave_sync();
         // convergence of the live chains: every |A_ij|, |Bm_ij| < tol
         if (live && r == 0) s_flag[gi] = 0;
         wave_sync();
@@ -780,10 +782,10 @@ __global__ __launch_bounds__(64) void k_decimate(DecArgs Dg) {
             bool big = false;
             gl_row<B>(MA, r, xr, xi);
 #pragma unroll
-            for (int j = 0; j < B; ++j) big |= !(hypot(xr[j], xi[j]) < D.tol);
+            for (int j = 0; j < B; ++j) big |= !(hypot(xr[j], xi[j]) < tol);
             gl_row<B>(MB, r, xr, xi);
 #pragma unroll
-            for (int j = 0; j < B; ++j) big |= !(hypot(xr[j], xi[j]) < D.tol);
+            for (int j = 0; j < B; ++j) big |= !(hypot(xr[j], xi[j]) < tol);
             if (big) s_flag[gi] = 1;
         }
         wave_sync();
@@ -793,38 +795,173 @@ __global__ __launch_bounds__(64) void k_decimate(DecArgs Dg) {
     }
     const bool converged = act && !live;
 
-    // surface block: P=1: g_s = (z - eps_s)^{-1};  P=2: g_s00 = (z - D0 - V (z - e11)^{-1} V^H)^{-1}
     live = act;
-    if (D.period == 1) {
-        inv_from(E1, false, L0);
-    } else {
-        inv_from(E1, false, L0);
-        if (live) gl_row<B>(D.V, r, xr, xi);
-        row_mul<T, B>(xr, xi, L0, ur, ui);
-        mul_uniform(D.VH);
-        wave_sync();
-        inv_from(D.D, true, L0);
+    inv_from(E1, L0);                                 // g_s = (z - eps_s)^{-1}
+    if (act) sigma_row<B, B>(J.tau[lead], L0, r, J.sigma + ((size_t)k * 2 + lead) * B * B);
+    if (act && r == 0) {
+        J.iters[(size_t)k * 2 + lead] = it_done;
+        if (!converged) atomicOr(&J.status[k], 1);
     }
-    // Sigma = tau g tau^H
-    if (live) gl_row<B>(D.tau, r, xr, xi);
-    row_mul<T, B>(xr, xi, L0, ur, ui);
-    if (live) {
+}
+
+template <int B>
+__global__ __launch_bounds__(64) void k_decimate(Sched S) {
+    constexpr int G = 64 / B;
+    __shared__ cx<double> s_buf[3][G][B * B];
+    __shared__ cx<double> s_prow[G][B];
+    __shared__ unsigned s_keys[G][B];
+    __shared__ int s_flag[G];
+    const int lane = threadIdx.x;
+    const int gi = lane / B;
+    Unit u;
+    // chain state is per workgroup: chains of earlier units are finished
+    cx<double>* sc_wg = S.scratch + (size_t)blockIdx.x * G * 4 * B * B;
+    while (next_unit<G>(S, u)) {
+        const JobDesc& J = S.jobs[u.job];
+        const bool act = (gi < G) && (gi < u.cnt);
+        const int k = u.e0 + (act ? gi : 0);
+        cx<double>* sc = sc_wg + (size_t)(gi < G ? gi : 0) * 4 * B * B;
+        decimate_chain1<B>(J, u.side, S.tol, S.maxit, k, act, sc, s_buf, s_prow, s_keys, s_flag);
+        wave_sync();
+    }
+}
+
+// ---- P = 2: group of 2B lanes per chain.  Lane q < B owns row q of the top
+// half of z - eps ([z-e00 | -V]) and row q of e00 and Bm; lane B+i owns row i
+// of the bottom half ([-V^H | z-e11]) and row i of e11 and A.  A and Bm are
+// also kept in LDS as right operands; the layer Green's function g lands in
+// the group's 2B x 2B stage.
+template <int B>
+__global__ __launch_bounds__(64) void k_decimate2(Sched S) {
+    constexpr int BB = 2 * B;
+    constexpr int G = 64 / BB;
+    __shared__ cx<double> s_g[G][BB * BB];
+    __shared__ cx<double> s_A[G][B * B];
+    __shared__ cx<double> s_Bm[G][B * B];
+    __shared__ cx<double> s_prow[G][BB];
+    __shared__ unsigned s_keys[G][BB];
+    __shared__ int s_flag[G];
+    const int lane = threadIdx.x;
+    const int gi = lane / BB;
+    const int gsafe = gi < G ? gi : 0;
+    const int q = lane - gi * BB;          // row of the layer matrix
+    const bool top = q < B;
+    const int i = top ? q : q - B;         // row inside the ring block
+    cx<double>* Sg = s_g[gsafe];
+    cx<double>* SA = s_A[gsafe];
+    cx<double>* SB = s_Bm[gsafe];
+
+    Unit u;
+    while (next_unit<G>(S, u)) {
+        const JobDesc& J = S.jobs[u.job];
+        const int lead = u.side;
+        const bool act = (gi < G) && (gi < u.cnt);
+        const int k = u.e0 + (act ? gi : 0);
+        const cx<double> z = J.z[k];
+        const cx<double>* D = J.D[lead];
+        const cx<double>* V = J.V[lead];
+        const cx<double>* VH = J.VH[lead];
+        const cx<double>* W = J.W[lead];
+
+        // e row (e00 on top lanes, e11 on bottom lanes), A = W, Bm = W^H
+        double er[B], ei[B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) { dr[j] = T(0); di[j] = T(0); }
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
+        for (int j = 0; j < B; ++j) { er[j] = 0.0; ei[j] = 0.0; }
+        wave_sync();
+        if (act) {
+            gl_row<B>(D + (top ? 0 : B * B), i, er, ei);
 #pragma unroll
             for (int j = 0; j < B; ++j) {
-                const cx<double> h = D.tau[j * B + q];       // tau^H[q][j] = conj(tau[j][q])
-                dr[j] += ur[q] * h.re + ui[q] * h.im;
-                di[j] += ui[q] * h.re - ur[q] * h.im;
+                if (top) { const cx<double> w = W[j * B + i]; SB[i * B + j] = cx<double>{w.re, -w.im}; }
+                else SA[i * B + j] = W[i * B + j];
             }
         }
-        gs_row<B>(Dg.sigma + ((size_t)k * 2 + lead) * B * B, r, dr, di);
-        if (r == 0) {
-            Dg.iters[(size_t)k * 2 + lead] = it_done;
-            if (!converged) atomicOr(&Dg.status[k], 1);
+        wave_sync();
+
+        // row q of z - eps, eps = [[e, V],[V^H, e']] with the e row in (er, ei)
+        auto layer_row = [&](double (&mr)[BB], double (&mi)[BB]) {
+#pragma unroll
+            for (int j = 0; j < BB; ++j) { mr[j] = 0.0; mi[j] = 0.0; }
+            if (act) {
+                const cx<double>* cpl = (top ? V : VH) + i * B;
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const cx<double> c = cpl[j];
+                    const int jd = top ? j : B + j;      // diagonal block column
+                    const int jc = top ? B + j : j;      // coupling block column
+                    mr[jd] = (j == i ? z.re : 0.0) - er[j];
+                    mi[jd] = (j == i ? z.im : 0.0) - ei[j];
+                    mr[jc] = -c.re;
+                    mi[jc] = -c.im;
+                }
+            }
+        };
+
+        bool live = act;
+        int it_done = S.maxit;
+        for (int it = 1; it <= S.maxit; ++it) {
+            {
+                double mr[BB], mi[BB];
+                layer_row(mr, mi);
+                Grp<double, BB> g{q, live, Sg, s_prow[gsafe], s_keys[gsafe]};
+                gj_inverse<double, BB>(mr, mi, g);        // Sg = g = (z - eps)^{-1}
+            }
+            // top row i:    e00 += (Bm g11) A,  Bm' = (Bm g10) Bm
+            // bottom row i: e11 += (A g00) Bm,  A'  = (A g01) A
+            double xr[B], xi[B], tr[B], ti[B], nr[B], ni[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const cx<double> x = top ? SB[i * B + j] : SA[i * B + j];
+                xr[j] = x.re;
+                xi[j] = x.im;
+            }
+            const cx<double>* g_diag = Sg + (top ? B * BB + B : 0);   // g11 (top) / g00 (bottom)
+            const cx<double>* g_off = Sg + (top ? B * BB : B);        // g10 (top) / g01 (bottom)
+            row_mul_ld<B, BB>(xr, xi, g_diag, tr, ti);
+            row_mul_ld<B, B>(tr, ti, top ? SA : SB, nr, ni);
+            if (live) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) { er[j] += nr[j]; ei[j] += ni[j]; }
+            }
+            row_mul_ld<B, BB>(xr, xi, g_off, tr, ti);
+            row_mul_ld<B, B>(tr, ti, top ? SB : SA, nr, ni);
+            wave_sync();
+            if (live) {
+                cx<double>* dst = (top ? SB : SA) + i * B;
+#pragma unroll
+                for (int j = 0; j < B; ++j) dst[j] = cx<double>{nr[j], ni[j]};
+            }
+            // convergence of the live chains: every |A_ij|, |Bm_ij| < tol
+            if (live && q == 0) s_flag[gi] = 0;
+            wave_sync();
+            if (live) {
+                bool big = false;
+#pragma unroll
+                for (int j = 0; j < B; ++j) big |= !(hypot(nr[j], ni[j]) < S.tol);
+                if (big) s_flag[gi] = 1;
+            }
+            wave_sync();
+            if (live && s_flag[gi] == 0) { live = false; it_done = it; }
+            wave_sync();
+            if (__all(!live)) break;
         }
+        const bool converged = act && !live;
+
+        // surface layer: eps_s = [[D0, V],[V^H, e11]]
+        live = act;
+        if (act && top) gl_row<B>(D, i, er, ei);
+        {
+            double mr[BB], mi[BB];
+            layer_row(mr, mi);
+            Grp<double, BB> g{q, live, Sg, s_prow[gsafe], s_keys[gsafe]};
+            gj_inverse<double, BB>(mr, mi, g);
+        }
+        if (act && top) sigma_row<B, BB>(J.tau[lead], Sg, i, J.sigma + ((size_t)k * 2 + lead) * B * B);
+        if (act && q == 0) {
+            J.iters[(size_t)k * 2 + lead] = it_done;
+            if (!converged) atomicOr(&J.status[k], 1);
+        }
+        wave_sync();
     }
 }
 

@@ -6,39 +6,47 @@
 
 namespace negf {
 
+enum { KIND_DECIMATE = 0, KIND_DECIMATE2, KIND_RECUR64, KIND_RECUR32, KIND_CDIAG64, KIND_CDIAG32, KIND_COLUMN64, KIND_COLUMN32,
+       KIND_COUNT };
+
 struct Launchers {
     int B;
-    int groups;   // chains per wavefront (64 / B)
-    void (*decimate)(const DecArgs&, int grid, hipStream_t);
-    void (*recur64)(const RgfArgs&, int grid, hipStream_t);
-    void (*recur32)(const RgfArgs&, int grid, hipStream_t);
-    void (*cdiag64)(const RgfArgs&, int nc_chunk, int grid, hipStream_t);
-    void (*cdiag32)(const RgfArgs&, int nc_chunk, int grid, hipStream_t);
-    void (*column64)(const RgfArgs&, int er0, int nr_chunk, int grid, hipStream_t);
-    void (*column32)(const RgfArgs&, int er0, int nr_chunk, int grid, hipStream_t);
+    int groups;                  // chains per wavefront (64 / B)
+    // launch[kind](sched, grid, dynamic LDS bytes, stream)
+    void (*launch[KIND_COUNT])(const Sched&, int grid, size_t dyn, hipStream_t);
+    const void* func[KIND_COUNT];   // kernel symbols (occupancy queries)
 };
 
 template <int B>
 struct LaunchImpl {
-    static void decimate(const DecArgs& a, int grid, hipStream_t s) {
+    static void decimate(const Sched& a, int grid, size_t, hipStream_t s) {
         hipLaunchKernelGGL(k_decimate<B>, dim3(grid), dim3(64), 0, s, a);
     }
+    static void decimate2(const Sched& a, int grid, size_t, hipStream_t s) {
+        hipLaunchKernelGGL(k_decimate2<B>, dim3(grid), dim3(64), 0, s, a);
+    }
     template <typename T>
-    static void recur(const RgfArgs& a, int grid, hipStream_t s) {
-        const size_t dyn = (size_t)a.n_uniq * B * a.K * (sizeof(cx<T>) + 1);
+    static void recur(const Sched& a, int grid, size_t dyn, hipStream_t s) {
         hipLaunchKernelGGL((k_recur<T, B>), dim3(grid), dim3(64), dyn, s, a);
     }
     template <typename T>
-    static void cdiag(const RgfArgs& a, int nc, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_cdiag<T, B>), dim3(grid), dim3(64), 0, s, a, nc);
+    static void cdiag(const Sched& a, int grid, size_t, hipStream_t s) {
+        hipLaunchKernelGGL((k_cdiag<T, B>), dim3(grid), dim3(64), 0, s, a);
     }
-    template <typename T, typename S>
-    static void column(const RgfArgs& a, int er0, int nr, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_column<T, S, B>), dim3(grid), dim3(64), 0, s, a, er0, nr);
+    template <typename T>
+    static void column(const Sched& a, int grid, size_t, hipStream_t s) {
+        hipLaunchKernelGGL((k_column<T, B>), dim3(grid), dim3(64), 0, s, a);
     }
     static const Launchers* table() {
-        static const Launchers t = {B, 64 / B, &decimate, &recur<double>, &recur<float>,
-                                    &cdiag<double>, &cdiag<float>, &column<double, double>, &column<float, float>};
+        static const Launchers t = {
+            B, 64 / B,
+            {&decimate, &decimate2, &recur<double>, &recur<float>, &cdiag<double>, &cdiag<float>, &column<double>,
+             &column<float>},
+            {reinterpret_cast<const void*>(&k_decimate<B>), reinterpret_cast<const void*>(&k_decimate2<B>),
+             reinterpret_cast<const void*>(&k_recur<double, B>),
+             reinterpret_cast<const void*>(&k_recur<float, B>), reinterpret_cast<const void*>(&k_cdiag<double, B>),
+             reinterpret_cast<const void*>(&k_cdiag<float, B>), reinterpret_cast<const void*>(&k_column<double, B>),
+             reinterpret_cast<const void*>(&k_column<float, B>)}};
         return &t;
     }
 };

@@ -1,4 +1,5 @@
-// Energy-sum kernels (Eq. 4-5) and small helpers; used by the C-ABI unit only.
+// Energy-sum kernels (Eq. 4-5) and per-job helpers; used by the C-ABI unit only.
+// Every kernel covers all jobs of a solve (job index = blockIdx.y or .z).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -6,23 +7,25 @@
 
 namespace negf {
 
-// ============================================================ reductions ==
-struct RedArgs {
+struct RedJob {
     int Nb, n_c, n_r;
-    double g_s;
+    double g_s, eta;
     double mu_L, mu_R, kT_L, kT_R;
-    const cx<double>* z_c;     // [n_c]
+    const cx<double>* z_c;     // [n_c] inputs (device)
     const cx<double>* w_c;     // [n_c]
     const double* E_r;         // [n_r]
     const double* w_r;         // [n_r]
+    cx<double>* z;             // [n_c + n_r] node array of the job (written by k_nodes)
     cx<double>* coef_c;        // [n_c]   w_c F(z_c - mu_min; kT_min)
     double* coef_r;            // [n_r][3] w fL, w fR, w (fL - fR)
-    const void* gr_diag;       // [n_c][Nb] cx<T>
-    const void* a_diag;        // [n_r][2][Nb] T
+    const void* gr_diag;       // [n_c][Nb] cx<TG>
+    const void* a_diag;        // [n_r][2][Nb] TA
     const double* T;           // [n_r]
+    double* part;              // [RED_SEGS][Nb]
     double* charge;            // [Nb]
     double* current;           // [1] or null
-    int* flags;                // [1] bit 2: non-finite output
+    const int* status;         // [n_c + n_r] decimation status
+    int* flags;                // [2]: bit 1 no convergence, bit 2 non-finite; first bad node
 };
 
 __device__ __forceinline__ double fermi_real(double E, double mu, double kT) {
@@ -44,7 +47,20 @@ __device__ __forceinline__ cx<double> fermi_cplx(cx<double> z, double mu, double
     return cx<double>{(nr * dr + ni * di) / den, (ni * dr - nr * di) / den};
 }
 
-__global__ void k_coef(RedArgs R) {
+// node array (contour nodes as given, real nodes E + i eta), status and flags reset
+__global__ void k_nodes(const RedJob* jobs, int* status_all, int status_n) {
+    const RedJob& J = jobs[blockIdx.y];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < J.n_c) J.z[e] = J.z_c[e];
+    else if (e < J.n_c + J.n_r) J.z[e] = cx<double>{J.E_r[e - J.n_c], J.eta};
+    if (blockIdx.y == 0) {
+        for (int i = e; i < status_n; i += gridDim.x * blockDim.x) status_all[i] = 0;
+    }
+    if (e == 0) { J.flags[0] = 0; J.flags[1] = 0x7fffffff; }
+}
+
+__global__ void k_coef(const RedJob* jobs) {
+    const RedJob& R = jobs[blockIdx.y];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const double mu_min = fmin(R.mu_L, R.mu_R), kT_min = fmin(R.kT_L, R.kT_R);
     if (e < R.n_c) {
@@ -60,15 +76,20 @@ __global__ void k_coef(RedArgs R) {
         R.coef_r[3 * q + 1] = w * fr;
         R.coef_r[3 * q + 2] = w * (fl - fr);
     }
+    if (e < R.n_c + R.n_r && R.status[e]) {
+        atomicOr(R.flags, R.status[e]);
+        atomicMin(R.flags + 1, e);
+    }
 }
 
 // charge_i in two fixed-order passes: energy segment `seg` (a fixed split of the
-// node index range) is summed in index order into part[seg][i], then the
-// segments are added in order.  The result depends only on the node list.
+// job's node index range) is summed in index order into part[seg][i], then the
+// segments are added in order.  The result depends only on the job's node list.
 constexpr int RED_SEGS = 32;
 
 template <typename TG, typename TA>
-__global__ void k_reduce_part(RedArgs R, double* part) {
+__global__ void k_reduce_part(const RedJob* jobs) {
+    const RedJob& R = jobs[blockIdx.z];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int seg = blockIdx.y;
     if (i >= R.Nb) return;
@@ -90,21 +111,23 @@ __global__ void k_reduce_part(RedArgs R, double* part) {
         }
     }
     const double inv_pi = 0.31830988618379067154;
-    part[(size_t)seg * R.Nb + i] = -inv_pi * acc_c + 0.5 * inv_pi * acc_r;
+    R.part[(size_t)seg * R.Nb + i] = -inv_pi * acc_c + 0.5 * inv_pi * acc_r;
 }
 
-__global__ void k_reduce_final(RedArgs R, const double* part) {
+__global__ void k_reduce_final(const RedJob* jobs) {
+    const RedJob& R = jobs[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R.Nb) return;
     double acc = 0.0;
-    for (int seg = 0; seg < RED_SEGS; ++seg) acc += part[(size_t)seg * R.Nb + i];
+    for (int seg = 0; seg < RED_SEGS; ++seg) acc += R.part[(size_t)seg * R.Nb + i];
     const double ch = R.g_s * acc;
     R.charge[i] = ch;
     if (!isfinite(ch)) atomicOr(R.flags, 2);
 }
 
-// current: one wavefront, lane l sums nodes l, l+64, ... then a fixed tree
-__global__ __launch_bounds__(64) void k_current(RedArgs R) {
+// current: one wavefront per job, lane l sums nodes l, l+64, ... then a fixed tree
+__global__ __launch_bounds__(64) void k_current(const RedJob* jobs) {
+    const RedJob& R = jobs[blockIdx.x];
     __shared__ double red[64];
     const int l = threadIdx.x;
     double acc = 0.0;
@@ -123,20 +146,9 @@ __global__ __launch_bounds__(64) void k_current(RedArgs R) {
     }
 }
 
-// prepares the node array: contour nodes as given, real nodes E + i eta
-__global__ void k_nodes(const cx<double>* z_c, int n_c, const double* E_r, int n_r, double eta, cx<double>* z) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n_c) z[e] = z_c[e];
-    else if (e < n_c + n_r) z[e] = cx<double>{E_r[e - n_c], eta};
-}
-
-// folds per-energy decimation status into the flag word
-__global__ void k_status(const int* status, int n, int* flags, int* first_bad) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n && status[e]) {
-        atomicOr(flags, status[e]);
-        atomicMin(first_bad, e);
-    }
+__global__ void k_fill_int(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 }  // namespace negf

@@ -26,6 +26,9 @@ EXPORTED = [
     "negf_default_options", "negf_create_device", "negf_set_potential", "negf_set_potential_dev",
     "negf_solve", "negf_solve_ex", "negf_solve_dev", "negf_sync", "negf_lead_self_energy",
     "negf_set_profiling", "negf_kernel_times", "negf_device_bytes", "negf_destroy", "negf_last_error",
+    "negf_workspace_create", "negf_workspace_destroy", "negf_workspace_bytes", "negf_workspace_set_profiling",
+    "negf_workspace_kernel_times", "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev",
+    "negf_batch_sync",
 ]
 
 
@@ -55,6 +58,12 @@ class negf_bias(C.Structure):
 class negf_outputs(C.Structure):
     _fields_ = [("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p), ("gr_diag", C.c_void_p),
                 ("al_diag", C.c_void_p), ("ar_diag", C.c_void_p), ("decim_iters", C.c_void_p)]
+
+
+class negf_job(C.Structure):
+    _fields_ = [("dev", C.c_void_p), ("bias", negf_bias), ("n_c", C.c_int), ("z_c", C.c_void_p),
+                ("w_c", C.c_void_p), ("n_r", C.c_int), ("E_r", C.c_void_p), ("w_r", C.c_void_p),
+                ("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p)]
 
 
 _lib = None
@@ -88,6 +97,21 @@ def load(path: str = LIB_PATH):
     lib.negf_destroy.restype = None
     lib.negf_last_error.argtypes = []
     lib.negf_last_error.restype = C.c_char_p
+    lib.negf_workspace_create.argtypes = [C.POINTER(vp), sz]
+    lib.negf_workspace_destroy.argtypes = [vp]
+    lib.negf_workspace_destroy.restype = None
+    lib.negf_workspace_bytes.argtypes = [vp]
+    lib.negf_workspace_bytes.restype = sz
+    lib.negf_workspace_set_profiling.argtypes = [vp, i]
+    lib.negf_workspace_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(d), C.POINTER(i),
+                                                C.POINTER(i)]
+    lib.negf_workspace_set_grid_scale.argtypes = [vp, i]
+    lib.negf_batch_solve.argtypes = [vp, i, C.POINTER(negf_job)]
+    lib.negf_batch_solve_dev.argtypes = [vp, i, C.POINTER(negf_job), vp]
+    lib.negf_batch_sync.argtypes = [vp, C.POINTER(i)]
+    for name in ("negf_workspace_create", "negf_workspace_set_profiling", "negf_workspace_kernel_times",
+                 "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev", "negf_batch_sync"):
+        getattr(lib, name).restype = C.c_int
     for name in ("negf_create_device", "negf_set_potential", "negf_set_potential_dev", "negf_solve",
                  "negf_solve_ex", "negf_solve_dev", "negf_sync", "negf_lead_self_energy", "negf_set_profiling",
                  "negf_kernel_times"):
@@ -220,15 +244,107 @@ class NegfDevice:
         _check(load().negf_set_profiling(self.h, 1 if on else 0))
 
     def kernel_times(self) -> dict:
-        n = C.c_int(16)
-        names = (C.c_char_p * 16)()
-        ms = (C.c_double * 16)()
-        calls = (C.c_int * 16)()
-        _check(load().negf_kernel_times(self.h, names, ms, calls, C.byref(n)))
-        return {names[k].decode(): (ms[k], calls[k]) for k in range(n.value)}
+        return _kernel_times(load().negf_kernel_times, self.h)
 
     def device_bytes(self) -> int:
         return int(load().negf_device_bytes(self.h))
+
+
+def _kernel_times(fn, h) -> dict:
+    n = C.c_int(16)
+    names = (C.c_char_p * 16)()
+    ms = (C.c_double * 16)()
+    calls = (C.c_int * 16)()
+    _check(fn(h, names, ms, calls, C.byref(n)))
+    return {names[k].decode(): (ms[k], calls[k]) for k in range(min(16, n.value))}
+
+
+@dataclass
+class Job:
+    """One entry of a batch: a device handle, its bias and its energy grid."""
+    dev: NegfDevice
+    bias: Bias
+    grid: EnergyGrid
+
+
+class Workspace:
+    """negf_workspace: batched solves of many devices in the same launches."""
+
+    def __init__(self, store_bytes: int = 0):
+        h = C.c_void_p()
+        _check(load().negf_workspace_create(C.byref(h), int(store_bytes)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().negf_workspace_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def bytes(self) -> int:
+        return int(load().negf_workspace_bytes(self.h))
+
+    def set_profiling(self, on: bool):
+        _check(load().negf_workspace_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        return _kernel_times(load().negf_workspace_kernel_times, self.h)
+
+    def set_grid_scale(self, scale: int):
+        _check(load().negf_workspace_set_grid_scale(self.h, int(scale)))
+
+    def solve(self, jobs) -> list:
+        """Host-array batch (synchronous); returns one SolveResult per job."""
+        keep, arr, res = [], (negf_job * len(jobs))(), []
+        for k, jb in enumerate(jobs):
+            g = jb.grid
+            zc, wc = _c(g.z_c, np.complex128), _c(g.w_c, np.complex128)
+            Er, wr = _c(g.E_r, np.float64), _c(g.w_r, np.float64)
+            charge, T, cur = np.zeros(jb.dev.N * jb.dev.b), np.zeros(Er.shape[0]), np.zeros(1)
+            keep += [zc, wc, Er, wr]
+            arr[k] = negf_job(jb.dev.h, negf_bias(jb.bias.mu_L, jb.bias.mu_R, jb.bias.kT_L, jb.bias.kT_R),
+                              zc.shape[0], _ptr(zc), _ptr(wc), Er.shape[0], _ptr(Er), _ptr(wr), _ptr(charge),
+                              _ptr(T), _ptr(cur))
+            res.append(SolveResult(charge, T, 0.0))
+            res[-1]._cur = cur
+        _check(load().negf_batch_solve(self.h, len(jobs), arr))
+        for r in res:
+            r.current = float(r._cur[0])
+            del r._cur
+        return res
+
+    def solve_dev(self, jobs, stream=None):
+        """Device batch: jobs are dicts with dev, bias, zc, wc, Er, wr, charge, T, current (tensors)."""
+        arr = (negf_job * len(jobs))()
+        for k, jb in enumerate(jobs):
+            b = jb["bias"]
+            zc, Er = jb.get("zc"), jb.get("Er")
+            arr[k] = negf_job(jb["dev"].h, negf_bias(b.mu_L, b.mu_R, b.kT_L, b.kT_R),
+                              0 if zc is None else int(zc.shape[0]), _tp(zc), _tp(jb.get("wc")),
+                              0 if Er is None else int(Er.shape[0]), _tp(Er), _tp(jb.get("wr")),
+                              _tp(jb["charge"]), _tp(jb.get("T")), _tp(jb.get("current")))
+        _check(load().negf_batch_solve_dev(self.h, len(jobs), arr, _stream_handle(stream)))
+
+    def sync(self) -> int:
+        """Waits for the last device batch; raises on a device-side error (attribute .job names it)."""
+        fj = C.c_int(-1)
+        st = load().negf_batch_sync(self.h, C.byref(fj))
+        if st != NEGF_OK:
+            e = NegfError(st, load().negf_last_error().decode())
+            e.job = fj.value
+            raise e
+        return fj.value
 
 
 def _tp(t):

@@ -319,3 +319,21 @@ def subsample_grid(grid: EnergyGrid, n_c: int, n_r: int, seed: int) -> EnergyGri
 def with_grid(p: Problem, grid: EnergyGrid, name: Optional[str] = None) -> Problem:
     return Problem(name or p.name + "_sub", p.device, p.U, p.U_left, p.U_right, p.bias, grid,
                    p.eta, p.decim_tol, p.decim_max_iter, p.g_s, dict(p.meta))
+
+
+def batch_problems(n_dev: int = 64, seed: int = 4040, chiralities=(10, 13, 17, 20, 23),
+                   N_range=(200, 2000), ne_range=(512, 4096), contour_frac: float = 0.25,
+                   V: float = 0.3) -> list:
+    """Many zigzag tubes of uneven chirality, length and node count: n drawn
+    from `chiralities`, N uniform in N_range, node count uniform in ne_range
+    (a quarter on the contour, the rest on the real axis), each with its own
+    tanh gate barrier."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_dev):
+        n = int(rng.choice(chiralities))
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        ne = int(rng.integers(ne_range[0], ne_range[1] + 1))
+        n_c = int(round(contour_frac * ne))
+        out.append(device_problem(N=N, n=n, seed=int(seed * 1000 + k), n_c=n_c, n_r=ne - n_c, V=V))
+    return out

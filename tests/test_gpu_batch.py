@@ -1,0 +1,181 @@
+"""Batched persistent solves: many uneven devices in the same launches.
+
+A job's results must be bit-identical to its solo solve (the arithmetic of a
+node never depends on which other chains share a launch), for any chunking of
+the recursion store and any persistent grid size; a batch that mixes ring
+sizes, lengths, node counts and precisions is checked against the oracle too.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import negf_oracle as O
+from paper_2407_14633_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def small_batch(seed=7, n_dev=7):
+    """Every chirality of the batching workload, short tubes, small grids."""
+    ps = W.batch_problems(n_dev, seed, N_range=(9, 48), ne_range=(6, 30))
+    chir = (10, 13, 17, 20, 23)
+    # make sure each ring size appears at least once
+    for k, n in enumerate(chir):
+        if all(p.meta["n"] != n for p in ps):
+            ps.append(W.device_problem(N=11 + 3 * k, n=n, seed=900 + k, n_c=4 + k, n_r=9 + k))
+    return ps
+
+
+def open_devices(negf, ps, precisions=None):
+    out = []
+    for k, p in enumerate(ps):
+        prec = negf.FP64 if precisions is None else precisions[k]
+        d = negf.NegfDevice(p.device, precision=prec, eta=p.eta, decim_tol=p.decim_tol,
+                            decim_max_iter=p.decim_max_iter, g_s=p.g_s)
+        d.set_potential(p.U, p.U_left, p.U_right)
+        out.append(d)
+    return out
+
+
+def solo(devs, ps):
+    return [d.solve(p.bias, p.grid) for d, p in zip(devs, ps)]
+
+
+def assert_same(a, b, what):
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x.charge, y.charge), f"{what}: job {k} charge differs"
+        assert np.array_equal(x.T, y.T), f"{what}: job {k} T differs"
+        assert x.current == y.current, f"{what}: job {k} current differs"
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "mixed"])
+def test_batch_bitwise_equals_solo(gpu_lib, mode):
+    negf = gpu_lib
+    ps = small_batch()
+    precs = {"fp64": [negf.FP64] * len(ps), "fp32": [negf.FP32_BULK] * len(ps),
+             "mixed": [negf.FP64 if k % 2 else negf.FP32_BULK for k in range(len(ps))]}[mode]
+    say("batch vs solo", mode, [(p.meta["n"], p.meta["N"], p.grid.n_c, p.grid.n_r) for p in ps])
+    devs = open_devices(negf, ps, precs)
+    ref = solo(devs, ps)
+    with negf.Workspace() as ws:
+        got = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        assert_same(got, ref, f"batch[{mode}]")
+        # a second call on the same workspace (tables cached) is identical too
+        got2 = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        assert_same(got2, ref, f"batch[{mode}] repeat")
+    for d in devs:
+        d.close()
+
+
+def test_batch_matches_oracle(gpu_lib):
+    negf = gpu_lib
+    ps = small_batch(seed=11, n_dev=5)
+    devs = open_devices(negf, ps)
+    with negf.Workspace() as ws:
+        got = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+    for k, (p, g) in enumerate(zip(ps, got)):
+        ref = O.solve(p)
+        say("batch vs oracle", k, p.meta["n"], p.meta["N"], rel(g.charge, ref["charge"]),
+            abs(g.current - ref["current"]) / max(abs(ref["current"]), 1e-300))
+        assert rel(g.charge, ref["charge"]) < 1e-10
+        assert abs(g.current - ref["current"]) <= 1e-10 * abs(ref["current"]) + 1e-22
+        assert rel(g.T, ref["T"]) < 1e-9
+    for d in devs:
+        d.close()
+
+
+def test_batch_chunking_and_grid_scale_invariant(gpu_lib):
+    negf = gpu_lib
+    ps = small_batch(seed=13, n_dev=6)
+    devs = open_devices(negf, ps)
+    jobs = [negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)]
+    with negf.Workspace() as ws:
+        ref = ws.solve(jobs)
+    # store cap of ~3 nodes of the longest tube: many chunks, spans split inside jobs
+    per = max(p.device.n_rings * p.device.b ** 2 * 16 for p in ps)
+    with negf.Workspace(store_bytes=3 * per + 17) as ws:
+        assert_same(ws.solve(jobs), ref, "chunked")
+    for scale in (2, 5):
+        with negf.Workspace() as ws:
+            ws.set_grid_scale(scale)
+            assert_same(ws.solve(jobs), ref, f"grid scale {scale}")
+    for d in devs:
+        d.close()
+
+
+def test_batch_device_pointers_equal_host(gpu_lib):
+    import torch
+    negf = gpu_lib
+    ps = small_batch(seed=17, n_dev=5)
+    devs = open_devices(negf, ps, [negf.FP64 if k % 2 else negf.FP32_BULK for k in range(len(ps))])
+    with negf.Workspace() as ws:
+        ref = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        dev = torch.device("cuda:0")
+        jobs, outs = [], []
+        for d, p in zip(devs, ps):
+            t = dict(dev=d, bias=p.bias,
+                     zc=torch.from_numpy(np.ascontiguousarray(p.grid.z_c)).to(dev),
+                     wc=torch.from_numpy(np.ascontiguousarray(p.grid.w_c)).to(dev),
+                     Er=torch.from_numpy(np.ascontiguousarray(p.grid.E_r)).to(dev),
+                     wr=torch.from_numpy(np.ascontiguousarray(p.grid.w_r)).to(dev),
+                     charge=torch.zeros(p.device.n_rings * p.device.b, dtype=torch.float64, device=dev),
+                     T=torch.zeros(p.grid.n_r, dtype=torch.float64, device=dev),
+                     current=torch.zeros(1, dtype=torch.float64, device=dev))
+            jobs.append(t)
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        for rep in range(2):
+            ws.solve_dev(jobs, stream=s)
+            assert ws.sync() == -1
+            for k, (t, r) in enumerate(zip(jobs, ref)):
+                assert np.array_equal(t["charge"].cpu().numpy(), r.charge), f"job {k} charge (rep {rep})"
+                assert np.array_equal(t["T"].cpu().numpy(), r.T), f"job {k} T (rep {rep})"
+                assert float(t["current"].cpu()[0]) == r.current, f"job {k} current (rep {rep})"
+    for d in devs:
+        d.close()
+
+
+def test_batch_reports_failing_job(gpu_lib):
+    negf = gpu_lib
+    ps = small_batch(seed=19, n_dev=3)[:3]
+    devs = open_devices(negf, ps)
+    # job 1 gets a decimation limit that a real-axis node cannot meet
+    bad = negf.NegfDevice(ps[1].device, decim_max_iter=1)
+    bad.set_potential(ps[1].U)
+    devs[1].close()
+    devs[1] = bad
+    with negf.Workspace() as ws:
+        with pytest.raises(negf.NegfError) as ei:
+            ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        assert ei.value.status == negf.NEGF_ENOCONV
+        assert "job 1" in str(ei.value)
+        # the workspace stays usable
+        ok = ws.solve([negf.Job(devs[0], ps[0].bias, ps[0].grid)])
+        assert np.array_equal(ok[0].charge, devs[0].solve(ps[0].bias, ps[0].grid).charge)
+    for d in devs:
+        d.close()
+
+
+def test_batch_rejects_bad_jobs(gpu_lib):
+    negf = gpu_lib
+    p = small_batch(seed=23, n_dev=1)[0]
+    (d,) = open_devices(negf, [p])
+    with negf.Workspace() as ws:
+        with pytest.raises(negf.NegfError) as ei:
+            ws.solve([negf.Job(d, W.Bias(0.1, -0.1, 0.0, 0.0259), p.grid)])
+        assert ei.value.status == negf.NEGF_EINVAL
+        empty = W.EnergyGrid(np.zeros(0, complex), np.zeros(0, complex), np.zeros(0), np.zeros(0))
+        with pytest.raises(negf.NegfError):
+            ws.solve([negf.Job(d, p.bias, empty)])
+    d.close()
