@@ -1,6 +1,6 @@
 """Energy-point solve throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload device|small|device1000|device2000]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload device|small|device1000|device2000|batch]
                     [--no-cpu-baseline] [--no-fp32]
 
 One step = one full negf_solve_dev (decimation, both recursions, contour diagonals,
@@ -67,9 +67,11 @@ def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
     cdiag = n_c * N * inv
     # lead columns: per ring one propagation product and one W Gamma product (+ b^2 dots)
     column = 2 * n_r * (N * (mul + 8.0 * b * b) + (N - 1) * mul)
-    # decimation: per doubling step (period 2) 4 inverses + 14 products; final 2 inverses + 4 products
-    per_it = {1: 1 * inv + 6 * mul, 2: 4 * inv + 14 * mul}
-    fin = {1: inv + 2 * mul, 2: 2 * inv + 4 * mul}
+    # decimation per doubling step: period 1 one b x b inverse + 6 products; period 2 one
+    # 2b x 2b inverse (8 b x b inverse equivalents) + 8 products; the surface step
+    # repeats the inverse and adds tau g tau^H
+    per_it = {1: 1 * inv + 6 * mul, 2: 8 * inv + 8 * mul}
+    fin = {1: inv + 2 * mul, 2: 8 * inv + 2 * mul}
     dec = 0.0
     for l, ld in enumerate((p.device.left, p.device.right)):
         dec += per_it[ld.period] * float(decim_iters[:, l].sum()) + fin[ld.period] * len(decim_iters)
@@ -140,6 +142,115 @@ def run(p: W.Problem, precision: int, steps: int, warmup: int):
     return out
 
 
+def batch_flops(ps) -> dict:
+    """Recursion, contour-diagonal and lead-column flops of one batch solve (decimation
+    omitted: its step counts are per node and not fetched for batches)."""
+    tot = {"recur": 0.0, "cdiag": 0.0, "column": 0.0}
+    for p in ps:
+        f = algorithmic_flops(p, np.zeros((1, 2)))
+        for k in tot:
+            tot[k] += f[k]
+    return tot
+
+
+def run_batch(ps, precision: int, steps: int, warmup: int, grid_scale: int = 0):
+    """Times negf_batch_solve_dev over all problems of the batch, inputs resident in HBM."""
+    import torch
+    from paper_2407_14633_amd import negf
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype=dt)
+    devs, jobs = [], []
+    for p in ps:
+        d = negf.NegfDevice(p.device, precision=precision, eta=p.eta, decim_tol=p.decim_tol,
+                            decim_max_iter=p.decim_max_iter, g_s=p.g_s)
+        d.set_potential(p.U, p.U_left, p.U_right)
+        devs.append(d)
+        g = p.grid
+        jobs.append(dict(dev=d, bias=p.bias,
+                         zc=t(g.z_c.view(np.float64).reshape(-1, 2), torch.float64) if g.n_c else None,
+                         wc=t(g.w_c.view(np.float64).reshape(-1, 2), torch.float64) if g.n_c else None,
+                         Er=t(g.E_r, torch.float64) if g.n_r else None,
+                         wr=t(g.w_r, torch.float64) if g.n_r else None,
+                         charge=torch.zeros(p.device.n_rings * p.device.b, dtype=torch.float64, device=dev),
+                         T=torch.zeros(max(g.n_r, 1), dtype=torch.float64, device=dev),
+                         current=torch.zeros(1, dtype=torch.float64, device=dev)))
+    ws = negf.Workspace()
+    if grid_scale:
+        ws.set_grid_scale(grid_scale)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ws.solve_dev(jobs, stream)
+    ws.sync()
+    ws.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ws.solve_dev(jobs, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ws.sync()
+    times = ws.kernel_times()
+    out = dict(ms_per_step=1e3 * dt / steps, times=times, hbm_bytes=ws.bytes(),
+               current=[float(j["current"].item()) for j in jobs],
+               charge=[j["charge"].cpu().numpy() for j in jobs])
+    ws.close()
+    for d in devs:
+        d.close()
+    return out
+
+
+def bench_batch(a):
+    """Batched form: 64 tubes of uneven chirality, length and node count in the same launches."""
+    from paper_2407_14633_amd import negf
+    ps = W.batch_problems()
+    n_e = sum(p.grid.n_c + p.grid.n_r for p in ps)
+    log(f"batch: {len(ps)} devices, {n_e} nodes, rings {min(p.device.n_rings for p in ps)}-"
+        f"{max(p.device.n_rings for p in ps)}, chiralities {sorted(set(p.meta['n'] for p in ps))}")
+    flops = batch_flops(ps)
+    res = {}
+    for name, prec, peak in (("f64", negf.FP64, FP64_PEAK_TFLOPS), ("f32_bulk", negf.FP32_BULK, FP32_PEAK_TFLOPS)):
+        if name == "f32_bulk" and a.no_fp32:
+            continue
+        r = run_batch(ps, prec, a.steps, a.warmup)
+        ms, calls = r["times"]["recur"]
+        per_step = ms / a.steps          # a batch step runs one recursion launch per store chunk
+        ach = flops["recur"] / (per_step * 1e-3) / 1e12
+        log(f"batch {name} ms/step {r['ms_per_step']:.2f} kernels {r['times']} HBM workspace {r['hbm_bytes'] / 2**30:.1f} GiB")
+        res[name] = dict(r=r, value=n_e / (r["ms_per_step"] * 1e-3),
+                         roofline={"kernel": "recur", "bound": "alu", "achieved": round(ach, 4), "peak": peak,
+                                   "unit": "TFLOP/s", "frac": round(ach / peak, 5), "traffic": None,
+                                   "ms_per_step": round(per_step, 4), "launches_per_step": calls // a.steps,
+                                   "flops_per_step": flops["recur"]})
+    r64 = res["f64"]
+    line = {
+        "metric": METRIC, "value": r64["value"], "unit": "energy-point solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": r64["r"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(ps)} zigzag (n,0) tubes, n in {{10,13,17,20,23}}, 200-2000 rings, "
+                               f"512-4096 nodes each (25% contour), {n_e} nodes in one batched solve",
+                   "n_devices": len(ps), "n_nodes": n_e},
+        "roofline": r64["roofline"], "cpu_baseline": None,
+        "fp32_bulk": None if "f32_bulk" not in res else {
+            "value": res["f32_bulk"]["value"], "ms_per_step": res["f32_bulk"]["r"]["ms_per_step"],
+            "roofline": res["f32_bulk"]["roofline"],
+            # per job |I32 - I64| / |I64| over jobs carrying at least 1e-3 of the largest current,
+            # and the largest |I32 - I64| relative to that largest current
+            **_current_diffs(res["f32_bulk"]["r"]["current"], r64["r"]["current"])},
+        "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in r64["r"]["times"].items()},
+        "serving": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _current_diffs(c32, c64) -> dict:
+    c32, c64 = np.asarray(c32), np.asarray(c64)
+    big = np.max(np.abs(c64))
+    sel = np.abs(c64) >= 1e-3 * big
+    return {"current_rel_diff_vs_fp64_max": float(np.max(np.abs(c32 - c64)[sel] / np.abs(c64[sel]))),
+            "current_diff_vs_largest_current": float(np.max(np.abs(c32 - c64)) / big),
+            "jobs_compared": int(sel.sum())}
+
+
 def calibrate_copy(mib: int):
     """A plain device-to-device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -162,7 +273,7 @@ def measured_traffic(kernel: str, b: int, precision: str):
     src = os.path.join(ROOT, "paper_2407_14633_amd", "csrc", "negf_kernels.hpp")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     names = {"recur": f"negf::k_recur<double, {b}>", "cdiag": f"negf::k_cdiag<double, {b}>",
-             "column": f"negf::k_column<double, double, {b}>", "decimate": f"negf::k_decimate<{b}>"}
+             "column": f"negf::k_column<double, {b}>", "decimate": f"negf::k_decimate2<{b}>"}
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
         for line in open(path):
             if line.startswith("machine-readable: "):
@@ -207,6 +318,9 @@ def main():
               file=sys.stderr)
         raise SystemExit(2)
     from paper_2407_14633_amd import negf
+    if a.workload == "batch":
+        bench_batch(a)
+        return
     p = make_problem(a.workload)
     n_e = p.grid.n_c + p.grid.n_r
     log(f"workload {p.name}: N={p.device.n_rings} b={p.device.b} n_c={p.grid.n_c} n_r={p.grid.n_r}")

@@ -210,6 +210,38 @@ negf_status negf_batch_solve(negf_workspace *w, int n_jobs, const negf_job *jobs
 negf_status negf_batch_solve_dev(negf_workspace *w, int n_jobs, const negf_job *jobs, void *hip_stream);
 negf_status negf_batch_sync(negf_workspace *w, int *failed_job);
 
+/* ---------------------------------------------------------- schedules ----
+ * Knobs of the persistent launches; results are bit-identical for every
+ * setting.  order 0 runs the longest chains first, 1 keeps the caller's order. */
+typedef struct {
+    int grid_scale;        /* persistent workgroups per (resident workgroups x CUs) */
+    int order;
+    double ms_per_solve;   /* autotuner: measured time of the chosen setting        */
+} negf_schedule;
+
+negf_status negf_workspace_set_order(negf_workspace *w, int order);
+/* Times every schedule setting on this job list (reps solves each, device
+ * pointers, on hip_stream), keeps the fastest in w and returns it in *best. */
+negf_status negf_workspace_autotune(negf_workspace *w, int n_jobs, const negf_job *jobs, void *hip_stream,
+                                    int reps, negf_schedule *best);
+
+/* ------------------------------------------------------------- graphs ----
+ * A batch solve recorded once into a HIP graph and replayed with one launch.
+ * The graph owns a private workspace (store_bytes as in negf_workspace_create)
+ * and fixes the job list: device handles, biases, node counts and every
+ * pointer.  The contents behind the pointers may change between launches: a
+ * replay sees new potentials (negf_set_potential*), energy nodes and weights.
+ * The devices must outlive the graph.  hip_stream must be a created stream
+ * (capture is not possible on the null stream); creation runs one eager solve.
+ * Replays on one graph are serialised on the device; statuses via
+ * negf_graph_sync as in negf_batch_sync. */
+typedef struct negf_graph negf_graph;
+negf_status negf_graph_create(negf_graph **out, int n_jobs, const negf_job *jobs, size_t store_bytes,
+                              void *hip_stream);
+negf_status negf_graph_launch(negf_graph *g, void *hip_stream);
+negf_status negf_graph_sync(negf_graph *g, int *failed_job);
+void negf_graph_destroy(negf_graph *g);
+
 #ifdef __cplusplus
 }
 #endif

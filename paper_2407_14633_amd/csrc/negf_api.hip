@@ -101,7 +101,10 @@ struct negf_workspace {
     double ms[KT_COUNT] = {0};
     int calls[KT_COUNT] = {0};
     size_t bytes = 0;
+    // schedule knobs (results do not depend on them)
     int grid_scale = 1;       // persistent workgroups per (resident workgroups x CU)
+    int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
+    bool capturing = false;   // enqueue is being recorded into a graph
 };
 
 struct negf_device {
@@ -152,6 +155,7 @@ negf_status wait_prev(negf_workspace* w) {
 
 negf_status grow(negf_workspace* w, DBuf& buf, size_t bytes) {
     if (bytes <= buf.cap && buf.p) return NEGF_OK;
+    if (w->capturing) return fail(NEGF_EINVAL, "graph capture needs a workspace sized by an eager solve");
     if (buf.p) {
         TRY(wait_prev(w));   // the previous solve may still use it
         (void)hipFree(buf.p);
@@ -215,7 +219,7 @@ negf_status check_job(const negf_job& j, int idx, bool host) {
 
 void ev_begin(negf_workspace* w, hipStream_t s, hipEvent_t* a) {
     *a = nullptr;
-    if (!w->prof) return;
+    if (!w->prof || w->capturing) return;
     (void)hipEventCreate(a);
     (void)hipEventRecord(*a, s);
 }
@@ -258,7 +262,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                     bool decimation_only = false) {
     HIPCHK(hipSetDevice(w->dev_id));
     // a solve on another stream starts after the previous one (shared arrays)
-    HIPCHK(hipStreamWaitEvent(s, w->done, 0));
+    if (!w->capturing) HIPCHK(hipStreamWaitEvent(s, w->done, 0));
     // ---- per-job array layout
     std::vector<JobPlan> plan(n_jobs);
     size_t nodes = 0, sig = 0, gr64 = 0, gr32 = 0, ad64 = 0, ad32 = 0, part = 0;
@@ -299,6 +303,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     TRY(grow(w, w->part, part * 8));
     TRY(grow(w, w->flags, (size_t)n_jobs * 2 * 4));
     if (n_jobs > w->cap_flags) {
+        if (w->capturing) return fail(NEGF_EINVAL, "graph capture needs a workspace sized by an eager solve");
         TRY(wait_prev(w));
         if (w->h_flags) (void)hipHostFree(w->h_flags);
         w->h_flags = nullptr;
@@ -384,7 +389,8 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     std::vector<Group> groups;
     std::vector<int> order(n_jobs);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plan[a].d->N > plan[b].d->N; });
+    if (w->order == 0)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plan[a].d->N > plan[b].d->N; });
     for (int i : order) {
         negf_device* d = plan[i].d;
         const bool f32 = d->opt.precision == NEGF_FP32_BULK;
@@ -521,6 +527,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     const size_t o_sp = put(spans.data(), spans.size() * sizeof(negf::Span));
     const size_t o_fi = put(firsts.data(), firsts.size() * sizeof(int));
     if (img != w->last_tables || !w->tables.p) {
+        if (w->capturing) return fail(NEGF_EINVAL, "graph capture: job tables differ from the eager solve");
         TRY(grow(w, w->tables, img.size()));
         TRY(wait_prev(w));
         HIPCHK(hipMemcpy(w->tables.p, img.data(), img.size(), hipMemcpyHostToDevice));
@@ -579,7 +586,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     ev_end(w, KT_REDUCE, s, ev);
     HIPCHK(hipMemcpyAsync(w->h_flags, w->flags.p, (size_t)n_jobs * 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(w->done, s));
+    if (!w->capturing) HIPCHK(hipEventRecord(w->done, s));
     w->last_n_jobs = n_jobs;
     return NEGF_OK;
 }
@@ -1122,6 +1129,132 @@ negf_status negf_batch_sync(negf_workspace* w, int* failed_job) {
 negf_status negf_batch_solve(negf_workspace* w, int n_jobs, const negf_job* jobs) {
     TRY(check_batch(w, n_jobs, jobs, true));
     return solve_host(w, n_jobs, jobs, nullptr);
+}
+
+negf_status negf_workspace_set_order(negf_workspace* w, int order) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    if (order != 0 && order != 1) return fail(NEGF_EINVAL, "order must be 0 or 1");
+    w->order = order;
+    return NEGF_OK;
+}
+
+negf_status negf_workspace_autotune(negf_workspace* w, int n_jobs, const negf_job* jobs, void* hip_stream,
+                                    int reps, negf_schedule* best) {
+    TRY(check_batch(w, n_jobs, jobs, false));
+    if (reps < 1 || reps > 100) return fail(NEGF_EINVAL, "reps %d not in [1,100]", reps);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(hipSetDevice(w->dev_id));
+    // warm once: buffers and tables are sized before anything is timed
+    TRY(enqueue(w, n_jobs, jobs, s));
+    TRY(finish(w, nullptr));
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    const int scales[] = {1, 2, 4};
+    negf_schedule bs{1, 0, 0.0};
+    negf_status st = NEGF_OK;
+    for (int order = 0; order < 2 && st == NEGF_OK; ++order)
+        for (int sc : scales) {
+            w->grid_scale = sc;
+            w->order = order;
+            if ((st = enqueue(w, n_jobs, jobs, s)) != NEGF_OK || (st = finish(w, nullptr)) != NEGF_OK) break;
+            (void)hipEventRecord(t0, s);
+            for (int r = 0; r < reps && st == NEGF_OK; ++r) st = enqueue(w, n_jobs, jobs, s);
+            (void)hipEventRecord(t1, s);
+            if (st == NEGF_OK) st = finish(w, nullptr);
+            if (st != NEGF_OK) break;
+            float ms = 0.f;
+            if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+                st = fail(NEGF_EHIP, "autotune timing events failed");
+                break;
+            }
+            const double per = ms / reps;
+            if (bs.ms_per_solve == 0.0 || per < bs.ms_per_solve) bs = negf_schedule{sc, order, per};
+        }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    w->grid_scale = bs.grid_scale;
+    w->order = bs.order;
+    if (best) *best = bs;
+    return st;
+}
+
+}  // extern "C"
+
+struct negf_graph {
+    negf_workspace* ws = nullptr;   // private workspace: its buffers and tables never change
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int n_jobs = 0;
+    std::vector<int> max_iter;
+};
+
+extern "C" {
+
+void negf_graph_destroy(negf_graph* g) {
+    if (!g) return;
+    if (g->ws) (void)hipSetDevice(g->ws->dev_id);
+    if (g->ws) (void)hipEventSynchronize(g->ws->done);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    ws_destroy(g->ws);
+    delete g;
+}
+
+negf_status negf_graph_create(negf_graph** out, int n_jobs, const negf_job* jobs, size_t store_bytes,
+                              void* hip_stream) {
+    if (!out) return fail(NEGF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!hip_stream) return fail(NEGF_EINVAL, "graph capture needs a created stream (not the null stream)");
+    negf_graph* g = new negf_graph();
+    auto bail = [&](negf_status st) {
+        const std::string m = g_err;
+        negf_graph_destroy(g);
+        g_err = m;
+        return st;
+    };
+    negf_status st;
+    if ((st = ws_create(&g->ws, store_bytes)) != NEGF_OK) return bail(st);
+    if ((st = check_batch(g->ws, n_jobs, jobs, false)) != NEGF_OK) return bail(st);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // eager solve: sizes the buffers, uploads the tables, checks the jobs
+    if ((st = enqueue(g->ws, n_jobs, jobs, s)) != NEGF_OK) return bail(st);
+    if ((st = finish(g->ws, nullptr)) != NEGF_OK) return bail(st);
+    g->max_iter = g->ws->last_max_iter;
+    g->n_jobs = n_jobs;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(fail(NEGF_EHIP, "hipStreamBeginCapture failed"));
+    g->ws->capturing = true;
+    st = enqueue(g->ws, n_jobs, jobs, s);
+    g->ws->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    g->graph = graph;
+    if (st != NEGF_OK) return bail(st);
+    if (e != hipSuccess) return bail(fail(NEGF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e)));
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(NEGF_EHIP, "hipGraphInstantiate failed"));
+    g->ws->last_n_jobs = 0;
+    *out = g;
+    return NEGF_OK;
+}
+
+negf_status negf_graph_launch(negf_graph* g, void* hip_stream) {
+    if (!g || !g->exec) return fail(NEGF_EINVAL, "graph is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(hipSetDevice(g->ws->dev_id));
+    HIPCHK(hipStreamWaitEvent(s, g->ws->done, 0));
+    HIPCHK(hipGraphLaunch(g->exec, s));
+    HIPCHK(hipEventRecord(g->ws->done, s));
+    g->ws->last_n_jobs = g->n_jobs;
+    g->ws->last_max_iter = g->max_iter;
+    return NEGF_OK;
+}
+
+negf_status negf_graph_sync(negf_graph* g, int* failed_job) {
+    if (!g) return fail(NEGF_EINVAL, "graph is NULL");
+    HIPCHK(hipSetDevice(g->ws->dev_id));
+    return finish(g->ws, failed_job);
 }
 
 }  // extern "C"

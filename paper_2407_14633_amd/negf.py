@@ -28,7 +28,8 @@ EXPORTED = [
     "negf_set_profiling", "negf_kernel_times", "negf_device_bytes", "negf_destroy", "negf_last_error",
     "negf_workspace_create", "negf_workspace_destroy", "negf_workspace_bytes", "negf_workspace_set_profiling",
     "negf_workspace_kernel_times", "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev",
-    "negf_batch_sync",
+    "negf_batch_sync", "negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create",
+    "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy",
 ]
 
 
@@ -64,6 +65,10 @@ class negf_job(C.Structure):
     _fields_ = [("dev", C.c_void_p), ("bias", negf_bias), ("n_c", C.c_int), ("z_c", C.c_void_p),
                 ("w_c", C.c_void_p), ("n_r", C.c_int), ("E_r", C.c_void_p), ("w_r", C.c_void_p),
                 ("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p)]
+
+
+class negf_schedule(C.Structure):
+    _fields_ = [("grid_scale", C.c_int), ("order", C.c_int), ("ms_per_solve", C.c_double)]
 
 
 _lib = None
@@ -109,6 +114,16 @@ def load(path: str = LIB_PATH):
     lib.negf_batch_solve.argtypes = [vp, i, C.POINTER(negf_job)]
     lib.negf_batch_solve_dev.argtypes = [vp, i, C.POINTER(negf_job), vp]
     lib.negf_batch_sync.argtypes = [vp, C.POINTER(i)]
+    lib.negf_workspace_set_order.argtypes = [vp, i]
+    lib.negf_workspace_autotune.argtypes = [vp, i, C.POINTER(negf_job), vp, i, C.POINTER(negf_schedule)]
+    lib.negf_graph_create.argtypes = [C.POINTER(vp), i, C.POINTER(negf_job), sz, vp]
+    lib.negf_graph_launch.argtypes = [vp, vp]
+    lib.negf_graph_sync.argtypes = [vp, C.POINTER(i)]
+    lib.negf_graph_destroy.argtypes = [vp]
+    lib.negf_graph_destroy.restype = None
+    for name in ("negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create", "negf_graph_launch",
+                 "negf_graph_sync"):
+        getattr(lib, name).restype = C.c_int
     for name in ("negf_workspace_create", "negf_workspace_set_profiling", "negf_workspace_kernel_times",
                  "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev", "negf_batch_sync"):
         getattr(lib, name).restype = C.c_int
@@ -326,15 +341,18 @@ class Workspace:
 
     def solve_dev(self, jobs, stream=None):
         """Device batch: jobs are dicts with dev, bias, zc, wc, Er, wr, charge, T, current (tensors)."""
-        arr = (negf_job * len(jobs))()
-        for k, jb in enumerate(jobs):
-            b = jb["bias"]
-            zc, Er = jb.get("zc"), jb.get("Er")
-            arr[k] = negf_job(jb["dev"].h, negf_bias(b.mu_L, b.mu_R, b.kT_L, b.kT_R),
-                              0 if zc is None else int(zc.shape[0]), _tp(zc), _tp(jb.get("wc")),
-                              0 if Er is None else int(Er.shape[0]), _tp(Er), _tp(jb.get("wr")),
-                              _tp(jb["charge"]), _tp(jb.get("T")), _tp(jb.get("current")))
+        arr = _dev_jobs(jobs)
         _check(load().negf_batch_solve_dev(self.h, len(jobs), arr, _stream_handle(stream)))
+
+    def set_order(self, order: int):
+        _check(load().negf_workspace_set_order(self.h, int(order)))
+
+    def autotune(self, jobs, stream=None, reps: int = 2) -> negf_schedule:
+        """Times every schedule on these device jobs and keeps the fastest."""
+        best = negf_schedule()
+        _check(load().negf_workspace_autotune(self.h, len(jobs), _dev_jobs(jobs), _stream_handle(stream),
+                                              int(reps), C.byref(best)))
+        return best
 
     def sync(self) -> int:
         """Waits for the last device batch; raises on a device-side error (attribute .job names it)."""
@@ -345,6 +363,57 @@ class Workspace:
             e.job = fj.value
             raise e
         return fj.value
+
+
+def _dev_jobs(jobs):
+    arr = (negf_job * len(jobs))()
+    for k, jb in enumerate(jobs):
+        b = jb["bias"]
+        zc, Er = jb.get("zc"), jb.get("Er")
+        arr[k] = negf_job(jb["dev"].h, negf_bias(b.mu_L, b.mu_R, b.kT_L, b.kT_R),
+                          0 if zc is None else int(zc.shape[0]), _tp(zc), _tp(jb.get("wc")),
+                          0 if Er is None else int(Er.shape[0]), _tp(Er), _tp(jb.get("wr")),
+                          _tp(jb["charge"]), _tp(jb.get("T")), _tp(jb.get("current")))
+    return arr
+
+
+class Graph:
+    """negf_graph: one batch solve recorded into a HIP graph, replayed with one launch."""
+
+    def __init__(self, jobs, stream, store_bytes: int = 0):
+        h = C.c_void_p()
+        _check(load().negf_graph_create(C.byref(h), len(jobs), _dev_jobs(jobs), int(store_bytes),
+                                        _stream_handle(stream)))
+        self.h = h
+
+    def launch(self, stream):
+        _check(load().negf_graph_launch(self.h, _stream_handle(stream)))
+
+    def sync(self) -> int:
+        fj = C.c_int(-1)
+        st = load().negf_graph_sync(self.h, C.byref(fj))
+        if st != NEGF_OK:
+            e = NegfError(st, load().negf_last_error().decode())
+            e.job = fj.value
+            raise e
+        return fj.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().negf_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def _tp(t):

@@ -179,3 +179,80 @@ def test_batch_rejects_bad_jobs(gpu_lib):
         with pytest.raises(negf.NegfError):
             ws.solve([negf.Job(d, p.bias, empty)])
     d.close()
+
+
+def _device_jobs(negf, devs, ps):
+    import torch
+    dev = torch.device("cuda:0")
+    jobs = []
+    for d, p in zip(devs, ps):
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        jobs.append(dict(dev=d, bias=p.bias, zc=t(p.grid.z_c), wc=t(p.grid.w_c), Er=t(p.grid.E_r), wr=t(p.grid.w_r),
+                         charge=torch.zeros(p.device.n_rings * p.device.b, dtype=torch.float64, device=dev),
+                         T=torch.zeros(p.grid.n_r, dtype=torch.float64, device=dev),
+                         current=torch.zeros(1, dtype=torch.float64, device=dev)))
+    return jobs
+
+
+def _check_jobs(jobs, ref, what):
+    for k, (t, r) in enumerate(zip(jobs, ref)):
+        assert np.array_equal(t["charge"].cpu().numpy(), r.charge), f"{what}: job {k} charge"
+        assert np.array_equal(t["T"].cpu().numpy(), r.T), f"{what}: job {k} T"
+        assert float(t["current"].cpu()[0]) == r.current, f"{what}: job {k} current"
+
+
+def test_graph_replays_match_eager(gpu_lib):
+    import torch
+    negf = gpu_lib
+    ps = small_batch(seed=29, n_dev=5)
+    devs = open_devices(negf, ps, [negf.FP64 if k % 2 else negf.FP32_BULK for k in range(len(ps))])
+    with negf.Workspace() as ws:
+        ref = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+    jobs = _device_jobs(negf, devs, ps)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with negf.Graph(jobs, s) as g:
+        x = torch.randn(256, 256, device="cuda:0")
+        for rep in range(3):
+            for t in jobs:                       # poison the outputs between replays
+                for key in ("charge", "T", "current"):
+                    t[key].fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.launch(s)
+            assert g.sync() == -1
+            _check_jobs(jobs, ref, f"graph replay {rep}")
+            x = x @ x.T / 256.0                  # eager work between replays
+            torch.cuda.synchronize()
+        # a replay sees a new potential written in place
+        p0 = ps[0]
+        devs[0].set_potential(0.5 * p0.U, p0.U_left, p0.U_right)
+        solo = devs[0].solve(p0.bias, p0.grid)
+        g.launch(s)
+        g.sync()
+        _check_jobs(jobs[:1], [solo], "graph replay after set_potential")
+    for d in devs:
+        d.close()
+
+
+def test_autotune_keeps_results(gpu_lib):
+    import torch
+    negf = gpu_lib
+    ps = small_batch(seed=31, n_dev=6)
+    devs = open_devices(negf, ps)
+    with negf.Workspace() as ws:
+        ref = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        jobs = _device_jobs(negf, devs, ps)
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        best = ws.autotune(jobs, s, reps=1)
+        say("autotune", best.grid_scale, best.order, best.ms_per_solve)
+        assert best.grid_scale in (1, 2, 4) and best.order in (0, 1) and best.ms_per_solve > 0
+        ws.solve_dev(jobs, s)
+        ws.sync()
+        _check_jobs(jobs, ref, "after autotune")
+        ws.set_order(1)
+        ws.solve_dev(jobs, s)
+        ws.sync()
+        _check_jobs(jobs, ref, "caller order")
+    for d in devs:
+        d.close()
