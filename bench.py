@@ -242,6 +242,41 @@ def bench_batch(a):
     print(json.dumps(line), flush=True)
 
 
+def run_serving(n_req: int, rate: float, seed: int = 5555, precision=None, max_inflight: int = 64) -> dict:
+    """Poisson arrivals of self-consistent bias-point requests (devices drawn like the batch
+    workload, V_DS ~ U[0,0.6], V_GS ~ U[-0.5,0.5]) served with continuous batching."""
+    from paper_2407_14633_amd import negf
+    precision = negf.FP64 if precision is None else precision
+    reqs = W.serving_requests(n_req, seed)
+    arrivals = W.poisson_arrivals(n_req, rate, seed + 1)
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    with negf.Server(budget, max_inflight=max_inflight, store_bytes=8 << 30) as srv:
+        t0 = time.perf_counter()
+        ids = []
+        for r, t_arr in zip(reqs, arrivals):
+            delay = t_arr - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(r, precision=precision))
+        res = [srv.poll(i) for i in ids]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array([r["t_total_ms"] for r in res])
+    it = np.array([r["iterations"] for r in res])
+    ok = sum(r["status"] == negf.NEGF_OK for r in res)
+    nodes = sum(q.grid.n_c + q.grid.n_r for q in reqs)
+    return {"rate_req_per_s": rate, "requests": n_req, "converged": int(ok), "precision": "fp32_bulk"
+            if precision == negf.FP32_BULK else "f64",
+            "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+            "throughput_req_per_s": n_req / wall, "wall_s": wall,
+            "passes_mean": float(it.mean()), "passes_max": int(it.max()), "eta": reqs[0].eta, "tol": reqs[0].tol,
+            "node_solves_per_s": float(np.sum(it * np.array([q.grid.n_c + q.grid.n_r for q in reqs])) / wall),
+            "server_passes": st["passes"], "hbm_budget_gib": budget / 2**30,
+            "workload": f"{n_req} requests, {nodes} energy nodes in total, Poisson arrivals at {rate} req/s (seed {seed})"}
+
+
 def _current_diffs(c32, c64) -> dict:
     c32, c64 = np.asarray(c32), np.asarray(c64)
     big = np.max(np.abs(c64))
@@ -306,6 +341,10 @@ def main():
     ap.add_argument("--workload", default="device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--requests", type=int, default=16, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=10.0, help="serving: Poisson arrival rate (req/s)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-fp32", action="store_true", help="serving: FP32-bulk NEGF instead of FP64")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     a = ap.parse_args()
@@ -320,6 +359,15 @@ def main():
     from paper_2407_14633_amd import negf
     if a.workload == "batch":
         bench_batch(a)
+        return
+    if a.workload == "serving":
+        srv = run_serving(a.requests, a.rate, precision=negf.FP32_BULK if a.serving_fp32 else negf.FP64)
+        log("serving", srv)
+        print(json.dumps({"metric": METRIC, "value": srv["p99_latency_ms"], "unit": "ms (p99 request latency)",
+                          "n_gpus": 1, "steps": a.requests, "warmup": 0, "ms_per_step": srv["p50_latency_ms"],
+                          "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": srv["precision"],
+                          "data": "synthetic", "config": {"workload": srv["workload"]}, "serving": srv}),
+              flush=True)
         return
     p = make_problem(a.workload)
     n_e = p.grid.n_c + p.grid.n_r

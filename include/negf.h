@@ -46,7 +46,8 @@ typedef enum {
     NEGF_ENOMEM = -2,     /* device memory allocation failed               */
     NEGF_ENOCONV = -3,    /* decimation did not converge in decim_max_iter */
     NEGF_ESINGULAR = -4,  /* non-finite pivot or output                    */
-    NEGF_EHIP = -5        /* HIP runtime error                             */
+    NEGF_EHIP = -5,       /* HIP runtime error                             */
+    NEGF_PENDING = 1      /* negf_server_poll: the request has not finished */
 } negf_status;
 
 enum { NEGF_FP64 = 0, NEGF_FP32_BULK = 1 };
@@ -187,6 +188,13 @@ typedef struct {
     double *charge;            /* [N*b] output                                        */
     double *T;                 /* [n_r] output or NULL                                */
     double *current;           /* [1]   output or NULL                                */
+    negf_c64 *sigma_cache;     /* optional device array [n_c+n_r][2][b][b] of lead
+                                  self-energies (left, right) at the job's nodes      */
+    int sigma_mode;            /* 0: self-energies live in the workspace (default);
+                                  1: decimate and keep them in sigma_cache;
+                                  2: reuse sigma_cache, no decimation (valid while the
+                                     nodes, eta and the lead potentials are unchanged,
+                                     Eq. 2: Sigma depends on nothing else)            */
 } negf_job;
 
 /* Workspace for batches: recursion stores, per-node arrays and the job/span
@@ -241,6 +249,75 @@ negf_status negf_graph_create(negf_graph **out, int n_jobs, const negf_job *jobs
 negf_status negf_graph_launch(negf_graph *g, void *hip_stream);
 negf_status negf_graph_sync(negf_graph *g, int *failed_job);
 void negf_graph_destroy(negf_graph *g);
+
+/* ------------------------------------------------------------ serving ----
+ * Self-consistent bias points (Section 2.4, Algorithm 3) served with continuous
+ * batching.  A request is a device with flat leads, a bias point and a fixed
+ * energy grid.  The server iterates
+ *     rho_in -> Poisson -> U -> NEGF (batched with every running request) -> rho_out
+ *     -> Broyden's modified second method on rho (per-ring electron counts)
+ * until max_j |rho_in_j - rho_out_j| / (rho_in_j + rho_out_j) < tol, starting from
+ * rho_in = n_ref.  Electrostatics: per ring j, potential phi_j (V),
+ *     -(eps_1d/dz^2)(phi_{j+1} - 2 phi_j + phi_{j-1}) + c_gate (phi_j - V_GS)
+ *         = -e (rho_j - n_ref_j)/dz,   phi_{-1} = 0 (source), phi_N = V_DS (drain),
+ * and the electron potential energy U_j = -phi_j eV on every atom of ring j.  The
+ * source lead sits at U = 0 and level mu_S, the drain lead at U = -V_DS and level
+ * mu_S - V_DS, both at temperature kT.  Lead self-energies are decimated once per
+ * request and reused on every pass.  A request's results do not depend on the
+ * other requests that share its passes.
+ *
+ * Admission: first come first served while the estimated HBM footprint of the
+ * running requests fits hbm_budget minus the two recursion stores
+ * (2 x store_bytes, 0 = 8 GiB each); at most max_inflight run at once.  A request
+ * whose footprint alone exceeds the budget is refused at submission (ENOMEM).
+ * Submission copies every array.  The server's thread owns the GPU work on the
+ * device that was current at creation; all calls are thread-safe.
+ */
+typedef struct negf_server negf_server;
+
+typedef struct {
+    int n_rings, b;                       /* as negf_create_device (n_rings >= 2)       */
+    const negf_c64 *h_diag, *h_up;
+    const negf_lead *left, *right;
+    negf_options opt;                     /* precision, eta, decimation, g_s            */
+    double mu_S, kT, V_DS, V_GS;          /* eV, eV, V, V                               */
+    int n_c; const negf_c64 *z_c, *w_c;   /* energy grid as in negf_solve               */
+    int n_r; const double *E_r, *w_r;
+    double dz;                            /* ring spacing (m)                           */
+    double eps_1d;                        /* axial permittivity x area (F m)            */
+    double c_gate;                        /* gate capacitance per length (F/m)          */
+    const double *n_ref;                  /* [n_rings] electrons per ring when neutral  */
+    double zeta, tol;                     /* Broyden fraction; stopping norm            */
+    int history, max_iter;                /* stored Broyden columns (<= 32); pass limit */
+} negf_sc_request;
+
+typedef struct {
+    int status;          /* NEGF_OK: converged; NEGF_ENOCONV: pass limit or decimation;
+                            other: solve or HIP error                                      */
+    int iterations;      /* NEGF passes taken                                              */
+    double eps_max;      /* stopping norm of the last pass                                 */
+    double current;      /* A, at the last potential                                       */
+    double t_queue_ms, t_run_ms, t_total_ms;   /* submit->admit, admit->done, submit->done */
+} negf_sc_result;
+
+typedef struct {
+    int pending, running;
+    long long passes;
+    size_t hbm_used, hbm_budget, workspace_bytes;
+} negf_server_info;
+
+negf_status negf_server_create(negf_server **out, size_t hbm_budget, int max_inflight, size_t store_bytes);
+negf_status negf_server_submit(negf_server *s, const negf_sc_request *req, long long *id);
+/* Result of request id; wait = 0 returns NEGF_PENDING while it runs.  On NEGF_OK the
+ * request is released: charge[N*b] (per atom), U[N*b] (final potential energy) and
+ * eps_trace[iterations] (stopping norm of every pass, capacity max_iter) are filled
+ * when not NULL. */
+negf_status negf_server_poll(negf_server *s, long long id, int wait, negf_sc_result *res,
+                             double *charge, double *U, double *eps_trace);
+/* Queue and memory counters; returns the last fatal status of the server thread. */
+negf_status negf_server_stats(negf_server *s, negf_server_info *info);
+/* Stops admitting, finishes the running requests, cancels the queued ones, frees all. */
+void negf_server_destroy(negf_server *s);
 
 #ifdef __cplusplus
 }

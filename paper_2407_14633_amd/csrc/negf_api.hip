@@ -11,13 +11,12 @@
 #include <string>
 #include <vector>
 
-#include "negf.h"
-#include "negf_launch.hpp"
+#include "negf_internal.hpp"
 #include "negf_reduce.hpp"
 
 using negf::cx;
 
-namespace {
+namespace negf_host {
 
 thread_local std::string g_err;
 
@@ -30,18 +29,6 @@ negf_status fail(negf_status s, const char* fmt, ...) {
     g_err = buf;
     return s;
 }
-
-#define HIPCHK(expr)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(NEGF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
-
-#define TRY(expr)                       \
-    do {                                \
-        negf_status s_ = (expr);        \
-        if (s_ != NEGF_OK) return s_;   \
-    } while (0)
 
 const negf::Launchers* launchers_for(int b) {
     switch (b) {
@@ -60,74 +47,8 @@ bool finite_c(const negf_c64* p, size_t n) {
     return true;
 }
 
-enum { KT_DECIMATE = 0, KT_RECUR, KT_CDIAG, KT_COLUMN, KT_REDUCE, KT_COUNT };
 const char* const kKernelNames[KT_COUNT] = {"decimate", "recur", "cdiag", "column", "reduce"};
 
-struct LeadDev {
-    int period = 1;
-    std::vector<negf_c64> h_diag;   // host copy, lead potential added on upload
-    cx<double>* D = nullptr;        // [P][b][b] incl. lead potential
-    cx<double>* V = nullptr;        // h_up[0]
-    cx<double>* VH = nullptr;       // h_up[0]^H
-    cx<double>* W = nullptr;        // h_up[P-1]
-    cx<double>* tau = nullptr;
-};
-
-// A growable device buffer (contents are not preserved when it grows).
-struct DBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-};
-
-}  // namespace
-
-struct negf_workspace {
-    int dev_id = 0;
-    size_t store_cap = 0;     // bytes per recursion store direction; 0 = default
-    int cus = 0;
-    DBuf tables, counters, z, sigma, iters, status, coef_c, coef_r, T, gr, ad, part, store_f, store_b, scratch,
-        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur;
-    std::vector<char> last_tables;   // host image of `tables` (re-uploaded only when it changes)
-    hipEvent_t done = nullptr;       // recorded after each enqueued solve
-    int* h_flags = nullptr;   // pinned [2 * cap_flags]
-    int cap_flags = 0;
-    int last_n_jobs = 0;
-    std::vector<int> last_max_iter;
-    hipStream_t own_stream = nullptr;
-    // profiling
-    bool prof = false;
-    struct Ev { int kind; hipEvent_t a, b; };
-    std::vector<Ev> pending;
-    double ms[KT_COUNT] = {0};
-    int calls[KT_COUNT] = {0};
-    size_t bytes = 0;
-    // schedule knobs (results do not depend on them)
-    int grid_scale = 1;       // persistent workgroups per (resident workgroups x CU)
-    int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
-    bool capturing = false;   // enqueue is being recorded into a graph
-};
-
-struct negf_device {
-    int dev_id = 0;
-    int N = 0, b = 0;
-    negf_options opt{};
-    const negf::Launchers* L = nullptr;
-    int K = 1, n_uniq = 1;
-    bool hdiag_zero = true;
-    double* d_U = nullptr;
-    cx<double>* d_hdiag = nullptr;
-    int* d_ell_map = nullptr;
-    int* d_cidx = nullptr;
-    cx<double>* d_cval = nullptr;
-    int* d_ridx = nullptr;
-    cx<double>* d_rval = nullptr;
-    LeadDev lead[2];
-    double U_lead[2] = {0.0, 0.0};
-    negf_workspace* ws = nullptr;   // private workspace of the single-device calls
-    size_t bytes = 0;
-};
-
-namespace {
 
 negf_status dalloc_raw(size_t* counter, void** p, size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -205,6 +126,8 @@ negf_status check_job(const negf_job& j, int idx, bool host) {
     if (j.n_c > 0 && (!j.z_c || !j.w_c)) return fail(NEGF_EINVAL, "job %d: contour nodes/weights are NULL", idx);
     if (j.n_r > 0 && (!j.E_r || !j.w_r)) return fail(NEGF_EINVAL, "job %d: real-axis nodes/weights are NULL", idx);
     if (!j.charge) return fail(NEGF_EINVAL, "job %d: charge output is NULL", idx);
+    if (j.sigma_mode < 0 || j.sigma_mode > 2) return fail(NEGF_EINVAL, "job %d: sigma_mode %d", idx, j.sigma_mode);
+    if (j.sigma_mode && !j.sigma_cache) return fail(NEGF_EINVAL, "job %d: sigma_cache is NULL", idx);
     if (host) {
         for (int i = 0; i < j.n_c; ++i)
             if (!std::isfinite(j.z_c[i].re) || !std::isfinite(j.z_c[i].im) || !std::isfinite(j.w_c[i].re) ||
@@ -258,8 +181,7 @@ struct JobPlan {
 };
 
 // Enqueues one solve of all jobs on stream s.  All job pointers are device pointers.
-negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStream_t s,
-                    bool decimation_only = false) {
+negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStream_t s, bool decimation_only) {
     HIPCHK(hipSetDevice(w->dev_id));
     // a solve on another stream starts after the previous one (shared arrays)
     if (!w->capturing) HIPCHK(hipStreamWaitEvent(s, w->done, 0));
@@ -336,7 +258,8 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         D.ridx = d->d_ridx;
         D.rval = d->d_rval;
         D.z = static_cast<cx<double>*>(w->z.p) + p.o_node;
-        D.sigma = static_cast<cx<double>*>(w->sigma.p) + p.o_sigma;
+        D.sigma = J.sigma_mode ? reinterpret_cast<cx<double>*>(J.sigma_cache)
+                               : static_cast<cx<double>*>(w->sigma.p) + p.o_sigma;
         D.gr_diag = f32 ? (void*)(gr_base + gr64 * 16 + p.o_gr * 8) : (void*)(gr_base + p.o_gr * 16);
         D.a_diag = f32 ? (void*)(ad_base + ad64 * 8 + p.o_ad * 4) : (void*)(ad_base + p.o_ad * 8);
         D.Tout = J.T ? J.T : static_cast<double*>(w->T.p) + p.o_node;
@@ -445,6 +368,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         {
             std::vector<negf::Span> sp[2][3];   // [period - 1][both, left only, right only]
             for (int j : g.ids) {
+                if (jobs[j].sigma_mode == 2) continue;   // cached self-energies
                 const int p0 = jd[j].period[0], p1 = jd[j].period[1];
                 if (p0 == p1) {
                     sp[p0 - 1][0].push_back({j, 0, plan[j].ne, 0, 0});
@@ -779,7 +703,9 @@ negf_status check_batch(negf_workspace* w, int n_jobs, const negf_job* jobs, boo
     return NEGF_OK;
 }
 
-}  // namespace
+}  // namespace negf_host
+
+using namespace negf_host;
 
 extern "C" {
 

@@ -1,0 +1,119 @@
+// Host-side internals shared by the C-ABI units (solves, batches, graphs, server).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "negf.h"
+#include "negf_launch.hpp"
+
+using negf::cx;
+
+namespace negf_host {
+
+extern thread_local std::string g_err;
+
+negf_status fail(negf_status s, const char* fmt, ...);
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(NEGF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+#define TRY(expr)                       \
+    do {                                \
+        negf_status s_ = (expr);        \
+        if (s_ != NEGF_OK) return s_;   \
+    } while (0)
+
+const negf::Launchers* launchers_for(int b);
+
+bool finite_c(const negf_c64* p, size_t n);
+
+enum { KT_DECIMATE = 0, KT_RECUR, KT_CDIAG, KT_COLUMN, KT_REDUCE, KT_COUNT };
+extern const char* const kKernelNames[KT_COUNT];
+
+struct LeadDev {
+    int period = 1;
+    std::vector<negf_c64> h_diag;   // host copy, lead potential added on upload
+    cx<double>* D = nullptr;        // [P][b][b] incl. lead potential
+    cx<double>* V = nullptr;        // h_up[0]
+    cx<double>* VH = nullptr;       // h_up[0]^H
+    cx<double>* W = nullptr;        // h_up[P-1]
+    cx<double>* tau = nullptr;
+};
+
+// A growable device buffer (contents are not preserved when it grows).
+struct DBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace negf_host
+
+using negf_host::DBuf;
+using negf_host::LeadDev;
+using negf_host::KT_COUNT;
+
+struct negf_workspace {
+    int dev_id = 0;
+    size_t store_cap = 0;     // bytes per recursion store direction; 0 = default
+    int cus = 0;
+    DBuf tables, counters, z, sigma, iters, status, coef_c, coef_r, T, gr, ad, part, store_f, store_b, scratch,
+        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur;
+    std::vector<char> last_tables;   // host image of `tables` (re-uploaded only when it changes)
+    hipEvent_t done = nullptr;       // recorded after each enqueued solve
+    int* h_flags = nullptr;   // pinned [2 * cap_flags]
+    int cap_flags = 0;
+    int last_n_jobs = 0;
+    std::vector<int> last_max_iter;
+    hipStream_t own_stream = nullptr;
+    // profiling
+    bool prof = false;
+    struct Ev { int kind; hipEvent_t a, b; };
+    std::vector<Ev> pending;
+    double ms[KT_COUNT] = {0};
+    int calls[KT_COUNT] = {0};
+    size_t bytes = 0;
+    // schedule knobs (results do not depend on them)
+    int grid_scale = 1;       // persistent workgroups per (resident workgroups x CU)
+    int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
+    bool capturing = false;   // enqueue is being recorded into a graph
+};
+
+struct negf_device {
+    int dev_id = 0;
+    int N = 0, b = 0;
+    negf_options opt{};
+    const negf::Launchers* L = nullptr;
+    int K = 1, n_uniq = 1;
+    bool hdiag_zero = true;
+    double* d_U = nullptr;
+    cx<double>* d_hdiag = nullptr;
+    int* d_ell_map = nullptr;
+    int* d_cidx = nullptr;
+    cx<double>* d_cval = nullptr;
+    int* d_ridx = nullptr;
+    cx<double>* d_rval = nullptr;
+    LeadDev lead[2];
+    double U_lead[2] = {0.0, 0.0};
+    negf_workspace* ws = nullptr;   // private workspace of the single-device calls
+    size_t bytes = 0;
+};
+
+
+namespace negf_host {
+
+negf_status grow(negf_workspace* w, DBuf& buf, size_t bytes);
+negf_status wait_prev(negf_workspace* w);
+negf_status check_job(const negf_job& j, int idx, bool host);
+negf_status check_batch(negf_workspace* w, int n_jobs, const negf_job* jobs, bool host);
+negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStream_t s,
+                    bool decimation_only = false);
+negf_status finish(negf_workspace* w, int* failed_job);
+negf_status ws_create(negf_workspace** out, size_t store_bytes);
+void ws_destroy(negf_workspace* w);
+
+}  // namespace negf_host

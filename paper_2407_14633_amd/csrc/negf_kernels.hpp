@@ -342,12 +342,45 @@ __device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r,
 // recursion y_{n+1} = c_n (a_n - y_n)^{-1} b_n; direction 1 (backward) runs the
 // right-connected x_{n-1} = b_{n-1} (a_n - x_n)^{-1} c_{n-1}, with
 // b_n = -H_{n,n+1}, c_n = -H_{n+1,n} (Algorithm 2 in blocks of M).
+// Boundary inversion of the FP32-bulk form: the row of (a_n - state) is built and
+// inverted in FP64, then rounded into the FP32 stage.  Used for the rings that
+// carry a lead self-energy: near a pole of Sigma (an edge state of the lead
+// surface) a_n - Sigma has entries far larger than its inverse's, and an FP32
+// inversion loses the small directions entirely.
+template <int B>
+__device__ __forceinline__ void invert_fp64_into(const JobDesc& J, int e, int n, int r, bool act, double uu,
+                                                 cx<double> z, cx<float>* stage, cx<double>* stage64,
+                                                 cx<double>* prow64, unsigned* keys) {
+    double kr[B], ki[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+        const cx<float> y = stage[r * B + j];
+        kr[j] = -(double)y.re;
+        ki[j] = -(double)y.im;
+    }
+    if (act) add_a_row<double, B>(J, e, n, r, uu, z, kr, ki);
+    Grp<double, B> g64{r, act, stage64, prow64, keys};
+    gj_inverse<double, B>(kr, ki, g64);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const cx<double> v = stage64[r * B + j];
+            stage[r * B + j] = cx<float>{(float)v.re, (float)v.im};
+        }
+    }
+    wave_sync();
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(64, 2) void k_recur(Sched S) {
     constexpr int G = 64 / B;
+    constexpr bool kF32 = sizeof(T) == 4;
+    constexpr int G64 = kF32 ? G : 1;   // FP64 boundary buffers (FP32-bulk form only)
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_prow[G][B];
     __shared__ unsigned s_keys[G][B];
+    __shared__ cx<double> s_stage64[G64][kF32 ? B * B : 1];
+    __shared__ cx<double> s_prow64[G64][kF32 ? B : 1];
     extern __shared__ unsigned char s_dyn[];
 
     const int lane = threadIdx.x;
@@ -393,11 +426,21 @@ __global__ __launch_bounds__(64, 2) void k_recur(Sched S) {
             if (last && __all(!act || contour)) break;
             const double uu = u_next;
             if (!last && act) u_next = J.U[(size_t)(dir ? N - 2 - s : s + 1) * B + r];
-            T kr[B], ki[B];
+            bool done64 = false;
+            if constexpr (kF32) {
+                if (s == 0 || last) {       // rings 0 and N-1 carry Sigma: invert in FP64
+                    invert_fp64_into<B>(J, e, n, r, act, uu, z, g.stage, s_stage64[gsafe], s_prow64[gsafe],
+                                        s_keys[gsafe]);
+                    done64 = true;
+                }
+            }
+            if (!done64) {
+                T kr[B], ki[B];
 #pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<T> y = g.stage[r * B + j]; kr[j] = -y.re; ki[j] = -y.im; }
-            if (act) add_a_row<T, B>(J, e, n, r, uu, z, kr, ki);
-            gj_inverse<T, B>(kr, ki, g);   // (a_n - y_n)^{-1} -> stage
+                for (int j = 0; j < B; ++j) { const cx<T> y = g.stage[r * B + j]; kr[j] = -y.re; ki[j] = -y.im; }
+                if (act) add_a_row<T, B>(J, e, n, r, uu, z, kr, ki);
+                gj_inverse<T, B>(kr, ki, g);   // (a_n - y_n)^{-1} -> stage
+            }
             if (last) {
                 // G_{N-1,N-1} (forward) / G_00 (backward): exact, the other side is empty
                 if (!contour) stage_to_global<T, B>(g.stage, store + (size_t)(dir ? N - 1 : 0) * B * B, r, act);
@@ -462,9 +505,13 @@ __global__ __launch_bounds__(64, 2) void k_recur(Sched S) {
 template <typename T, int B>
 __global__ __launch_bounds__(64, 2) void k_cdiag(Sched S) {
     constexpr int G = 64 / B;
+    constexpr bool kF32 = sizeof(T) == 4;
+    constexpr int G64 = kF32 ? G : 1;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_prow[G][B];
     __shared__ unsigned s_keys[G][B];
+    __shared__ cx<double> s_stage64[G64][kF32 ? B * B : 1];
+    __shared__ cx<double> s_prow64[G64][kF32 ? B : 1];
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
@@ -476,20 +523,52 @@ __global__ __launch_bounds__(64, 2) void k_cdiag(Sched S) {
         const JobDesc& J = S.jobs[u.job];
         const int N = J.N;
         const int n_items = S.spans[u.span].cnt * N;
-        const bool act = (gi < G) && (u.i0 + gi < n_items);
-        Grp<T, B> g{r, act, s_stage[gsafe], s_prow[gsafe], s_keys[gsafe]};
-        const int item = u.i0 + (act ? gi : 0);
+        const bool live = (gi < G) && (u.i0 + gi < n_items);
+        const int item = u.i0 + (live ? gi : 0);
         const int el = item / N;                 // node inside the span
         const int e = u.e0 + el;                 // node inside the job
         const int n = item - el * N;
+        const size_t o_row = u.off + ((size_t)el * N + n) * B * B + (size_t)r * B;
+        // FP32-bulk: the rings that carry a lead self-energy are inverted in FP64
+        const bool bnd = kF32 && (n == 0 || n == N - 1);
+        if constexpr (kF32) {
+            const bool act64 = live && bnd;
+            if (__any(act64)) {
+                double kr[B], ki[B];
+#pragma unroll
+                for (int j = 0; j < B; ++j) { kr[j] = 0.0; ki[j] = 0.0; }
+                if (act64) {
+                    const cx<T>* sf = reinterpret_cast<const cx<T>*>(S.store_f) + o_row;
+                    const cx<T>* sb = reinterpret_cast<const cx<T>*>(S.store_b) + o_row;
+                    if (n > 0) {
+#pragma unroll
+                        for (int j = 0; j < B; ++j) { const cx<T> v = sf[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                    }
+                    if (n < N - 1) {
+#pragma unroll
+                        for (int j = 0; j < B; ++j) { const cx<T> v = sb[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                    }
+                    add_a_row<double, B>(J, e, n, r, J.U[(size_t)n * B + r], J.z[e], kr, ki);
+                }
+                Grp<double, B> g64{r, act64, s_stage64[gsafe], s_prow64[gsafe], s_keys[gsafe]};
+                gj_inverse<double, B>(kr, ki, g64);
+                if (act64) {
+                    const cx<double> d = s_stage64[gsafe][r * B + r];
+                    reinterpret_cast<cx<T>*>(J.gr_diag)[(size_t)e * N * B + (size_t)n * B + r] =
+                        cx<T>{(T)d.re, (T)d.im};
+                }
+                wave_sync();
+            }
+        }
+        const bool act = live && !bnd;
+        Grp<T, B> g{r, act, s_stage[gsafe], s_prow[gsafe], s_keys[gsafe]};
 
         T kr[B], ki[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) { kr[j] = T(0); ki[j] = T(0); }
         if (act) {
-            const size_t o = u.off + ((size_t)el * N + n) * B * B + (size_t)r * B;
-            const cx<T>* sf = reinterpret_cast<const cx<T>*>(S.store_f) + o;
-            const cx<T>* sb = reinterpret_cast<const cx<T>*>(S.store_b) + o;
+            const cx<T>* sf = reinterpret_cast<const cx<T>*>(S.store_f) + o_row;
+            const cx<T>* sb = reinterpret_cast<const cx<T>*>(S.store_b) + o_row;
             if (n > 0) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) { const cx<T> v = sf[j]; kr[j] -= v.re; ki[j] -= v.im; }

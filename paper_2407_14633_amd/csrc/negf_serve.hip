@@ -1,0 +1,511 @@
+// Serving runtime: self-consistent bias-point requests solved with continuous
+// batching on one GPU.
+//
+// A native thread owns the GPU work.  Each pass of its loop
+//   1. admits queued requests, first come first served, while their estimated
+//      HBM footprint fits the budget (device, grid, self-energy cache,
+//      per-node energy arrays, mixing state);
+//   2. solves the NEGF step of every running request in one batched solve (the
+//      persistent kernels of the batch API; lead self-energies are decimated
+//      once per request and reused, since they depend only on the nodes and the
+//      lead potentials, which a bias point fixes);
+//   3. runs one self-consistency workgroup per request (ring charges, Broyden
+//      update, Poisson, new potential);
+//   4. retires requests that converged or hit their pass limit.
+// New requests join at the next pass while the others keep iterating, so their
+// work overlaps on the device.  A request's arithmetic never depends on the
+// others in the batch: its results are the same alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "negf_internal.hpp"
+#include "negf_sc.hpp"
+
+using namespace negf_host;
+
+namespace {
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct ScJob {
+    long long id = 0;
+    int slot = -1;
+    // host copy of the request
+    int N = 0, b = 0;
+    std::vector<negf_c64> h_diag, h_up, lead_hd[2], lead_hu[2], lead_tau[2];
+    int lead_period[2] = {1, 1};
+    negf_options opt{};
+    negf_bias bias{};
+    double V_DS = 0, V_GS = 0;
+    std::vector<negf_c64> z_c, w_c;
+    std::vector<double> E_r, w_r, n_ref;
+    double a = 0, c = 0, zeta = 0, tol = 0;
+    int H = 0, max_iter = 0;
+    size_t footprint = 0;
+    // device state
+    negf_device* dev = nullptr;
+    void* mem = nullptr;          // one allocation for grid, outputs, self-energies and mixing state
+    negf_c64 *d_zc = nullptr, *d_wc = nullptr, *d_sigma = nullptr;
+    double *d_Er = nullptr, *d_wr = nullptr, *d_charge = nullptr, *d_T = nullptr, *d_cur = nullptr;
+    double *d_nref = nullptr, *d_state = nullptr;
+    bool sigma_ready = false;
+    negf::ScReq rq{};
+    // results
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int status = NEGF_OK;
+    int passes = 0;
+    double eps_max = 0, current = 0;
+    bool done = false;
+    std::vector<double> charge_out, U_out;
+    std::vector<double> trace;    // stopping norm of every pass
+};
+
+}  // namespace
+
+struct negf_server {
+    int dev_id = 0;
+    size_t budget = 0, used = 0, fixed = 0;
+    int max_inflight = 0;
+    negf_workspace* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int* d_stat = nullptr;        // [max_inflight][4]
+    double* d_diag = nullptr;     // [max_inflight][2]
+    int* h_stat = nullptr;        // pinned copies
+    double* h_diag = nullptr;
+    negf::ScReq* d_reqs = nullptr;   // [max_inflight]
+    std::vector<int> free_slots;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    std::deque<ScJob*> pending;
+    std::vector<ScJob*> running;
+    std::map<long long, ScJob*> jobs;
+    long long next_id = 1;
+    negf_status fatal = NEGF_OK;
+    std::string fatal_msg;
+    long long passes = 0;
+};
+
+namespace {
+
+size_t estimate_footprint(const ScJob& j) {
+    const size_t Nb = (size_t)j.N * j.b, b2 = (size_t)j.b * j.b, ne = j.z_c.size() + j.E_r.size();
+    const bool f32 = j.opt.precision == NEGF_FP32_BULK;
+    size_t s = 0;
+    s += (size_t)j.N * b2 * 16 + Nb * 8 + 8192;                        // device Hamiltonian, potential, couplings
+    s += j.z_c.size() * 32 + j.E_r.size() * 16;                        // grid
+    s += Nb * 8 + j.E_r.size() * 8 + 8;                                // outputs
+    s += ne * 2 * b2 * 16;                                             // self-energy cache
+    s += (size_t)(8 + 2 * (j.H + 1)) * j.N * 8;                        // mixing state and Poisson scratch
+    s += j.z_c.size() * Nb * (f32 ? 8 : 16) + j.E_r.size() * 2 * Nb * (f32 ? 4 : 8);   // per-node diagonals
+    s += (size_t)32 * Nb * 8 + ne * 96;                                // reduction partials, per-node scalars
+    return s;
+}
+
+// frees the request's device memory; the caller returns its slot under the lock
+void release(ScJob* j) {
+    if (j->dev) negf_destroy(j->dev);
+    j->dev = nullptr;
+    if (j->mem) (void)hipFree(j->mem);
+    j->mem = nullptr;
+}
+
+negf_status setup(negf_server* S, ScJob* j) {
+    negf_lead leads[2];
+    for (int l = 0; l < 2; ++l)
+        leads[l] = negf_lead{j->lead_period[l], j->lead_hd[l].data(), j->lead_hu[l].data(), j->lead_tau[l].data()};
+    TRY(negf_create_device(&j->dev, j->N, j->b, j->h_diag.data(), j->N > 1 ? j->h_up.data() : nullptr, &leads[0],
+                           &leads[1], &j->opt));
+    std::vector<double> U0((size_t)j->N * j->b, 0.0);
+    TRY(negf_set_potential(j->dev, U0.data(), 0.0, -j->V_DS));
+    const size_t nc = j->z_c.size(), nr = j->E_r.size(), ne = nc + nr, N = j->N, Nb = N * j->b;
+    const size_t b2 = (size_t)j->b * j->b;
+    const size_t n_state = 5 * N + 2 * (size_t)(j->H + 1) * N + 3 * N;
+    // ten sub-arrays, each rounded up to 256 bytes
+    const size_t bytes = nc * 32 + ne * 2 * b2 * 16 + (2 * nr + Nb + std::max<size_t>(nr, 1) + 1 + N + n_state) * 8 +
+                         10 * 256;
+    HIPCHK(hipMalloc(&j->mem, bytes));
+    char* p = static_cast<char*>(j->mem);
+    auto take = [&](size_t n) { char* q = p; p += (n + 255) & ~size_t(255); return q; };
+    j->d_zc = reinterpret_cast<negf_c64*>(take(nc * 16));
+    j->d_wc = reinterpret_cast<negf_c64*>(take(nc * 16));
+    j->d_sigma = reinterpret_cast<negf_c64*>(take(ne * 2 * b2 * 16));
+    j->d_Er = reinterpret_cast<double*>(take(nr * 8));
+    j->d_wr = reinterpret_cast<double*>(take(nr * 8));
+    j->d_charge = reinterpret_cast<double*>(take(Nb * 8));
+    j->d_T = reinterpret_cast<double*>(take(std::max<size_t>(nr, 1) * 8));
+    j->d_cur = reinterpret_cast<double*>(take(8));
+    j->d_nref = reinterpret_cast<double*>(take(N * 8));
+    j->d_state = reinterpret_cast<double*>(take(n_state * 8));
+    if (nc) {
+        HIPCHK(hipMemcpy(j->d_zc, j->z_c.data(), nc * 16, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(j->d_wc, j->w_c.data(), nc * 16, hipMemcpyHostToDevice));
+    }
+    if (nr) {
+        HIPCHK(hipMemcpy(j->d_Er, j->E_r.data(), nr * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(j->d_wr, j->w_r.data(), nr * 8, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(j->d_nref, j->n_ref.data(), N * 8, hipMemcpyHostToDevice));
+    negf::ScReq& R = j->rq;
+    R.N = j->N;
+    R.b = j->b;
+    R.H = j->H;
+    R.max_iter = j->max_iter;
+    R.zeta = j->zeta;
+    R.tol = j->tol;
+    R.a = j->a;
+    R.c = j->c;
+    R.V_GS = j->V_GS;
+    R.V_DS = j->V_DS;
+    R.charge = j->d_charge;
+    R.U = j->dev->d_U;
+    R.n_ref = j->d_nref;
+    double* st = j->d_state;
+    R.rho_in = st;
+    R.rho_in_old = st + N;
+    R.f_old = st + 2 * N;
+    R.s = st + 3 * N;
+    R.Vt = st + 5 * N;
+    R.Wc = st + 5 * N + (size_t)(j->H + 1) * N;
+    R.work = st + 5 * N + 2 * (size_t)(j->H + 1) * N;
+    R.stat = S->d_stat + 4 * j->slot;
+    R.diag = S->d_diag + 2 * j->slot;
+    return NEGF_OK;
+}
+
+negf_job job_of(ScJob* j) {
+    negf_job q{};
+    q.dev = j->dev;
+    q.bias = j->bias;
+    q.n_c = (int)j->z_c.size();
+    q.z_c = j->d_zc;
+    q.w_c = j->d_wc;
+    q.n_r = (int)j->E_r.size();
+    q.E_r = j->d_Er;
+    q.w_r = j->d_wr;
+    q.charge = j->d_charge;
+    q.T = q.n_r ? j->d_T : nullptr;
+    q.current = j->d_cur;
+    q.sigma_cache = j->d_sigma;
+    q.sigma_mode = j->sigma_ready ? 2 : 1;
+    return q;
+}
+
+void finish_job(negf_server* S, ScJob* j, int status) {
+    j->status = status;
+    j->t_done = now_ms();
+    const size_t Nb = (size_t)j->N * j->b;
+    if (j->dev && j->mem) {
+        j->charge_out.resize(Nb);
+        j->U_out.resize(Nb);
+        if (hipMemcpy(j->charge_out.data(), j->d_charge, Nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(j->U_out.data(), j->dev->d_U, Nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&j->current, j->d_cur, 8, hipMemcpyDeviceToHost) != hipSuccess)
+            j->status = NEGF_EHIP;
+    }
+    release(j);
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (j->slot >= 0) S->free_slots.push_back(j->slot);
+    j->slot = -1;
+    S->used -= std::min(S->used, j->footprint);
+    j->done = true;
+    S->cv_done.notify_all();
+}
+
+// one pass over the running set; returns a non-OK status only for errors that stop the server
+negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
+    // set up the newly admitted requests and start their mixing state
+    std::vector<ScJob*> fresh;
+    for (ScJob* j : admitted) {
+        j->t_admit = now_ms();
+        const negf_status st = setup(S, j);
+        if (st != NEGF_OK) {
+            finish_job(S, j, st);
+            continue;
+        }
+        fresh.push_back(j);
+    }
+    admitted.clear();
+    if (!fresh.empty()) {
+        std::vector<negf::ScReq> rq;
+        for (ScJob* j : fresh) rq.push_back(j->rq);
+        HIPCHK(hipMemcpy(S->d_reqs, rq.data(), rq.size() * sizeof(negf::ScReq), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(negf::k_sc_step, dim3((unsigned)fresh.size()), dim3(negf::SC_THREADS), 0, S->stream,
+                           S->d_reqs, 0);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(S->stream));
+        for (ScJob* j : fresh) S->running.push_back(j);
+    }
+    if (S->running.empty()) return NEGF_OK;
+
+    // NEGF step of every running request, one batched solve
+    std::vector<negf_job> jobs;
+    for (ScJob* j : S->running) jobs.push_back(job_of(j));
+    TRY(enqueue(S->ws, (int)jobs.size(), jobs.data(), S->stream));
+    // self-consistency pass, one workgroup per request
+    std::vector<negf::ScReq> rq;
+    for (ScJob* j : S->running) rq.push_back(j->rq);
+    HIPCHK(hipMemcpyAsync(S->d_reqs, rq.data(), rq.size() * sizeof(negf::ScReq), hipMemcpyHostToDevice, S->stream));
+    hipLaunchKernelGGL(negf::k_sc_step, dim3((unsigned)rq.size()), dim3(negf::SC_THREADS), 0, S->stream, S->d_reqs,
+                       1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(S->h_stat, S->d_stat, (size_t)S->max_inflight * 4 * sizeof(int), hipMemcpyDeviceToHost,
+                          S->stream));
+    HIPCHK(hipMemcpyAsync(S->h_diag, S->d_diag, (size_t)S->max_inflight * 2 * sizeof(double),
+                          hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(hipEventRecord(S->ws->done, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));   // rq stays alive until the upload has run
+    S->passes++;
+    // per-request NEGF flags (bit 1: decimation, bit 2: non-finite result)
+    std::vector<ScJob*> keep;
+    for (size_t k = 0; k < S->running.size(); ++k) {
+        ScJob* j = S->running[k];
+        j->sigma_ready = true;
+        const int fl = S->ws->h_flags[2 * k];
+        const int* st = S->h_stat + 4 * j->slot;
+        j->passes = st[1];
+        j->eps_max = S->h_diag[2 * j->slot];
+        j->trace.push_back(j->eps_max);
+        if (fl) {
+            finish_job(S, j, (fl & 1) ? NEGF_ENOCONV : NEGF_ESINGULAR);
+        } else if (st[2] == 1) {
+            finish_job(S, j, NEGF_OK);
+        } else if (st[2] == 2) {
+            finish_job(S, j, NEGF_ENOCONV);
+        } else {
+            keep.push_back(j);
+        }
+    }
+    S->running.swap(keep);
+    S->ws->last_n_jobs = 0;
+    return NEGF_OK;
+}
+
+void server_loop(negf_server* S) {
+    (void)hipSetDevice(S->dev_id);
+    std::vector<ScJob*> admitted;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || !S->running.empty(); });
+            if (S->stop && S->running.empty()) {
+                for (ScJob* j : S->pending) {
+                    j->status = NEGF_EINVAL;
+                    j->done = true;
+                }
+                S->pending.clear();
+                S->cv_done.notify_all();
+                return;
+            }
+            while (!S->stop && !S->pending.empty() && (int)(S->running.size() + admitted.size()) < S->max_inflight) {
+                ScJob* j = S->pending.front();
+                if (S->used + j->footprint > S->budget && !(S->running.empty() && admitted.empty())) break;
+                S->pending.pop_front();
+                S->used += j->footprint;
+                j->slot = S->free_slots.back();
+                S->free_slots.pop_back();
+                admitted.push_back(j);
+            }
+        }
+        const negf_status st = server_pass(S, admitted);
+        if (st != NEGF_OK) {
+            // a HIP or allocation failure: fail the running requests and keep serving
+            const std::string msg = g_err;
+            for (ScJob* j : S->running) finish_job(S, j, st);
+            S->running.clear();
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->fatal = st;
+            S->fatal_msg = msg;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+negf_status negf_server_create(negf_server** out, size_t hbm_budget, int max_inflight, size_t store_bytes) {
+    if (!out) return fail(NEGF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_inflight < 1 || max_inflight > 4096) return fail(NEGF_EINVAL, "max_inflight %d not in [1,4096]",
+                                                             max_inflight);
+    negf_server* S = new negf_server();
+    auto bail = [&](negf_status st) {
+        const std::string m = g_err;
+        negf_server_destroy(S);
+        g_err = m;
+        return st;
+    };
+    if (hipGetDevice(&S->dev_id) != hipSuccess) return bail(fail(NEGF_EHIP, "no HIP device"));
+    S->max_inflight = max_inflight;
+    negf_status st;
+    if ((st = ws_create(&S->ws, store_bytes)) != NEGF_OK) return bail(st);
+    const size_t cap = store_bytes ? store_bytes : ((size_t)8 << 30);
+    S->fixed = 2 * cap;
+    if (hbm_budget <= S->fixed) return bail(fail(NEGF_EINVAL, "budget %zu bytes leaves nothing beyond the two "
+                                                             "recursion stores (%zu bytes)", hbm_budget, S->fixed));
+    S->budget = hbm_budget - S->fixed;
+    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(NEGF_EHIP, "stream creation failed"));
+    if (hipMalloc(&S->d_stat, (size_t)max_inflight * 4 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&S->d_diag, (size_t)max_inflight * 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&S->d_reqs, (size_t)max_inflight * sizeof(negf::ScReq)) != hipSuccess)
+        return bail(fail(NEGF_ENOMEM, "server tables"));
+    if (hipHostMalloc((void**)&S->h_stat, (size_t)max_inflight * 4 * sizeof(int), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&S->h_diag, (size_t)max_inflight * 2 * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess)
+        return bail(fail(NEGF_ENOMEM, "pinned server tables"));
+    for (int k = max_inflight - 1; k >= 0; --k) S->free_slots.push_back(k);
+    S->th = std::thread(server_loop, S);
+    *out = S;
+    return NEGF_OK;
+}
+
+negf_status negf_server_submit(negf_server* S, const negf_sc_request* r, long long* id) {
+    if (!S || !r || !id) return fail(NEGF_EINVAL, "NULL argument");
+    if (r->n_rings < 2) return fail(NEGF_EINVAL, "n_rings = %d < 2", r->n_rings);
+    if (r->b < 1 || r->b > NEGF_MAX_RING) return fail(NEGF_EINVAL, "ring size %d", r->b);
+    if (!r->h_diag || !r->h_up || !r->left || !r->right || !r->n_ref)
+        return fail(NEGF_EINVAL, "request has a NULL array");
+    if (r->n_c < 0 || r->n_r < 0 || r->n_c + r->n_r < 1) return fail(NEGF_EINVAL, "no energy nodes");
+    if ((r->n_c && (!r->z_c || !r->w_c)) || (r->n_r && (!r->E_r || !r->w_r)))
+        return fail(NEGF_EINVAL, "grid arrays are NULL");
+    if (!(r->dz > 0) || !(r->eps_1d > 0) || !(r->c_gate > 0)) return fail(NEGF_EINVAL, "electrostatics must be > 0");
+    if (!(r->zeta > 0) || !(r->tol > 0) || r->max_iter < 1 || r->history < 0 ||
+        r->history > negf::SC_MAX_HISTORY)
+        return fail(NEGF_EINVAL, "mixing settings out of range (history <= %d)", negf::SC_MAX_HISTORY);
+    if (!(r->kT > 0) || !std::isfinite(r->mu_S) || !std::isfinite(r->V_DS) || !std::isfinite(r->V_GS))
+        return fail(NEGF_EINVAL, "bias point not finite");
+    ScJob* j = new ScJob();
+    const int N = r->n_rings, b = r->b;
+    const size_t b2 = (size_t)b * b;
+    j->N = N;
+    j->b = b;
+    j->h_diag.assign(r->h_diag, r->h_diag + (size_t)N * b2);
+    j->h_up.assign(r->h_up, r->h_up + (size_t)(N - 1) * b2);
+    const negf_lead* ls[2] = {r->left, r->right};
+    for (int l = 0; l < 2; ++l) {
+        const int P = ls[l]->period;
+        if (P < 1 || P > NEGF_MAX_PERIOD || !ls[l]->h_diag || !ls[l]->h_up || !ls[l]->tau) {
+            delete j;
+            return fail(NEGF_EINVAL, "bad lead %d", l);
+        }
+        j->lead_period[l] = P;
+        j->lead_hd[l].assign(ls[l]->h_diag, ls[l]->h_diag + P * b2);
+        j->lead_hu[l].assign(ls[l]->h_up, ls[l]->h_up + P * b2);
+        j->lead_tau[l].assign(ls[l]->tau, ls[l]->tau + b2);
+    }
+    j->opt = r->opt;
+    j->V_DS = r->V_DS;
+    j->V_GS = r->V_GS;
+    j->bias = negf_bias{r->mu_S, r->mu_S - r->V_DS, r->kT, r->kT};
+    j->z_c.assign(r->z_c, r->z_c + r->n_c);
+    j->w_c.assign(r->w_c, r->w_c + r->n_c);
+    j->E_r.assign(r->E_r, r->E_r + r->n_r);
+    j->w_r.assign(r->w_r, r->w_r + r->n_r);
+    j->n_ref.assign(r->n_ref, r->n_ref + N);
+    const double e = 1.602176634e-19;
+    j->a = r->eps_1d / (r->c_gate * r->dz * r->dz);
+    j->c = e / (r->c_gate * r->dz);
+    j->zeta = r->zeta;
+    j->tol = r->tol;
+    j->H = r->history;
+    j->max_iter = r->max_iter;
+    j->footprint = estimate_footprint(*j);
+    j->t_submit = now_ms();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (j->footprint > S->budget) {
+        delete j;
+        return fail(NEGF_ENOMEM, "request footprint exceeds the server's HBM budget");
+    }
+    if (S->stop) {
+        delete j;
+        return fail(NEGF_EINVAL, "server is stopping");
+    }
+    j->id = S->next_id++;
+    S->jobs[j->id] = j;
+    S->pending.push_back(j);
+    *id = j->id;
+    S->cv_work.notify_all();
+    return NEGF_OK;
+}
+
+negf_status negf_server_poll(negf_server* S, long long id, int wait, negf_sc_result* res, double* charge,
+                             double* U, double* eps_trace) {
+    if (!S) return fail(NEGF_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    if (it == S->jobs.end()) return fail(NEGF_EINVAL, "unknown request %lld", id);
+    ScJob* j = it->second;
+    if (!j->done) {
+        if (!wait) return NEGF_PENDING;
+        S->cv_done.wait(lk, [&] { return j->done; });
+    }
+    if (res) {
+        res->status = j->status;
+        res->iterations = j->passes;
+        res->eps_max = j->eps_max;
+        res->current = j->current;
+        res->t_queue_ms = j->t_admit > 0 ? j->t_admit - j->t_submit : 0.0;
+        res->t_run_ms = j->t_admit > 0 ? j->t_done - j->t_admit : 0.0;
+        res->t_total_ms = j->t_done - j->t_submit;
+    }
+    if (charge && !j->charge_out.empty()) memcpy(charge, j->charge_out.data(), j->charge_out.size() * 8);
+    if (U && !j->U_out.empty()) memcpy(U, j->U_out.data(), j->U_out.size() * 8);
+    if (eps_trace && !j->trace.empty()) memcpy(eps_trace, j->trace.data(), j->trace.size() * 8);
+    S->jobs.erase(it);
+    delete j;
+    return NEGF_OK;
+}
+
+negf_status negf_server_stats(negf_server* S, negf_server_info* info) {
+    if (!S || !info) return fail(NEGF_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    info->pending = (int)S->pending.size();
+    info->running = (int)S->running.size();
+    info->passes = S->passes;
+    info->hbm_used = S->used + S->fixed;
+    info->hbm_budget = S->budget + S->fixed;
+    info->workspace_bytes = S->ws ? S->ws->bytes : 0;
+    return S->fatal;
+}
+
+void negf_server_destroy(negf_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv_work.notify_all();
+    }
+    if (S->th.joinable()) S->th.join();
+    (void)hipSetDevice(S->dev_id);
+    for (auto& kv : S->jobs) {
+        release(kv.second);
+        delete kv.second;
+    }
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    if (S->d_stat) (void)hipFree(S->d_stat);
+    if (S->d_diag) (void)hipFree(S->d_diag);
+    if (S->d_reqs) (void)hipFree(S->d_reqs);
+    if (S->h_stat) (void)hipHostFree(S->h_stat);
+    if (S->h_diag) (void)hipHostFree(S->h_diag);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    ws_destroy(S->ws);
+    delete S;
+}
+
+}  // extern "C"

@@ -18,9 +18,10 @@ from .workload import Bias, Device, EnergyGrid, Lead, Problem
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnegf.so")
 
 NEGF_OK, NEGF_EINVAL, NEGF_ENOMEM, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_EHIP = 0, -1, -2, -3, -4, -5
+NEGF_PENDING = 1
 FP64, FP32_BULK = 0, 1
 STATUS_NAMES = {0: "NEGF_OK", -1: "NEGF_EINVAL", -2: "NEGF_ENOMEM", -3: "NEGF_ENOCONV",
-                -4: "NEGF_ESINGULAR", -5: "NEGF_EHIP"}
+                -4: "NEGF_ESINGULAR", -5: "NEGF_EHIP", 1: "NEGF_PENDING"}
 
 EXPORTED = [
     "negf_default_options", "negf_create_device", "negf_set_potential", "negf_set_potential_dev",
@@ -29,7 +30,8 @@ EXPORTED = [
     "negf_workspace_create", "negf_workspace_destroy", "negf_workspace_bytes", "negf_workspace_set_profiling",
     "negf_workspace_kernel_times", "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev",
     "negf_batch_sync", "negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create",
-    "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy",
+    "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy", "negf_server_create", "negf_server_submit",
+    "negf_server_poll", "negf_server_stats", "negf_server_destroy",
 ]
 
 
@@ -64,11 +66,32 @@ class negf_outputs(C.Structure):
 class negf_job(C.Structure):
     _fields_ = [("dev", C.c_void_p), ("bias", negf_bias), ("n_c", C.c_int), ("z_c", C.c_void_p),
                 ("w_c", C.c_void_p), ("n_r", C.c_int), ("E_r", C.c_void_p), ("w_r", C.c_void_p),
-                ("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p)]
+                ("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p),
+                ("sigma_cache", C.c_void_p), ("sigma_mode", C.c_int)]
 
 
 class negf_schedule(C.Structure):
     _fields_ = [("grid_scale", C.c_int), ("order", C.c_int), ("ms_per_solve", C.c_double)]
+
+
+class negf_sc_request(C.Structure):
+    _fields_ = [("n_rings", C.c_int), ("b", C.c_int), ("h_diag", C.c_void_p), ("h_up", C.c_void_p),
+                ("left", C.c_void_p), ("right", C.c_void_p), ("opt", negf_options), ("mu_S", C.c_double),
+                ("kT", C.c_double), ("V_DS", C.c_double), ("V_GS", C.c_double), ("n_c", C.c_int),
+                ("z_c", C.c_void_p), ("w_c", C.c_void_p), ("n_r", C.c_int), ("E_r", C.c_void_p),
+                ("w_r", C.c_void_p), ("dz", C.c_double), ("eps_1d", C.c_double), ("c_gate", C.c_double),
+                ("n_ref", C.c_void_p), ("zeta", C.c_double), ("tol", C.c_double), ("history", C.c_int),
+                ("max_iter", C.c_int)]
+
+
+class negf_sc_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("eps_max", C.c_double), ("current", C.c_double),
+                ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+
+class negf_server_info(C.Structure):
+    _fields_ = [("pending", C.c_int), ("running", C.c_int), ("passes", C.c_longlong), ("hbm_used", C.c_size_t),
+                ("hbm_budget", C.c_size_t), ("workspace_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -121,6 +144,14 @@ def load(path: str = LIB_PATH):
     lib.negf_graph_sync.argtypes = [vp, C.POINTER(i)]
     lib.negf_graph_destroy.argtypes = [vp]
     lib.negf_graph_destroy.restype = None
+    lib.negf_server_create.argtypes = [C.POINTER(vp), sz, i, sz]
+    lib.negf_server_submit.argtypes = [vp, C.POINTER(negf_sc_request), C.POINTER(C.c_longlong)]
+    lib.negf_server_poll.argtypes = [vp, C.c_longlong, i, C.POINTER(negf_sc_result), vp, vp, vp]
+    lib.negf_server_stats.argtypes = [vp, C.POINTER(negf_server_info)]
+    lib.negf_server_destroy.argtypes = [vp]
+    lib.negf_server_destroy.restype = None
+    for name in ("negf_server_create", "negf_server_submit", "negf_server_poll", "negf_server_stats"):
+        getattr(lib, name).restype = C.c_int
     for name in ("negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create", "negf_graph_launch",
                  "negf_graph_sync"):
         getattr(lib, name).restype = C.c_int
@@ -373,7 +404,8 @@ def _dev_jobs(jobs):
         arr[k] = negf_job(jb["dev"].h, negf_bias(b.mu_L, b.mu_R, b.kT_L, b.kT_R),
                           0 if zc is None else int(zc.shape[0]), _tp(zc), _tp(jb.get("wc")),
                           0 if Er is None else int(Er.shape[0]), _tp(Er), _tp(jb.get("wr")),
-                          _tp(jb["charge"]), _tp(jb.get("T")), _tp(jb.get("current")))
+                          _tp(jb["charge"]), _tp(jb.get("T")), _tp(jb.get("current")),
+                          _tp(jb.get("sigma_cache")), int(jb.get("sigma_mode", 0)))
     return arr
 
 
@@ -439,3 +471,81 @@ def solve_problem(p: Problem, precision: int = FP64, details: bool = False, **kw
                     decim_max_iter=p.decim_max_iter, g_s=p.g_s, **kw) as d:
         d.set_potential(p.U, p.U_left, p.U_right)
         return d.solve(p.bias, p.grid, details=details)
+
+
+class Server:
+    """negf_server: self-consistent bias-point requests with continuous batching."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 64, store_bytes: int = 0):
+        h = C.c_void_p()
+        _check(load().negf_server_create(C.byref(h), int(hbm_budget), int(max_inflight), int(store_bytes)))
+        self.h = h
+        self._sizes = {}
+
+    def submit(self, req, precision: int = FP64) -> int:
+        """req: workload.ScRequest.  Returns the request id."""
+        dev, g, e = req.device, req.grid, req.elec
+        keep = []
+
+        def arr(a, dt):
+            a = _c(a, dt)
+            keep.append(a)
+            return _ptr(a)
+
+        def lead(ld):
+            return negf_lead(ld.period, arr(ld.h_diag, np.complex128), arr(ld.h_up, np.complex128),
+                             arr(ld.tau, np.complex128))
+
+        L, R = lead(dev.left), lead(dev.right)
+        o = default_options()
+        o.precision, o.eta, o.decim_tol, o.decim_max_iter, o.g_s = (precision, req.eta, req.decim_tol,
+                                                                      req.decim_max_iter, req.g_s)
+        r = negf_sc_request(dev.n_rings, dev.b, arr(dev.h_diag, np.complex128), arr(dev.h_up, np.complex128),
+                            C.cast(C.pointer(L), C.c_void_p), C.cast(C.pointer(R), C.c_void_p), o,
+                            req.bias.mu_L, req.bias.kT_L, e.V_DS, e.V_GS, g.n_c, arr(g.z_c, np.complex128),
+                            arr(g.w_c, np.complex128), g.n_r, arr(g.E_r, np.float64), arr(g.w_r, np.float64),
+                            e.dz, e.eps_1d, e.c_gate, arr(e.n_ref, np.float64), req.zeta, req.tol, req.history,
+                            req.max_iter)
+        rid = C.c_longlong()
+        _check(load().negf_server_submit(self.h, C.byref(r), C.byref(rid)))
+        self._sizes[rid.value] = (dev.n_rings * dev.b, req.max_iter)
+        return rid.value
+
+    def poll(self, rid: int, wait: bool = True):
+        """dict(status, iterations, eps_max, current, t_queue_ms, t_run_ms, t_total_ms, charge, U),
+        or None while the request runs (wait=False)."""
+        nb, mi = self._sizes.get(rid, (0, 0))
+        res = negf_sc_result()
+        charge, U, tr = np.zeros(nb), np.zeros(nb), np.zeros(max(mi, 1))
+        st = load().negf_server_poll(self.h, C.c_longlong(rid), 1 if wait else 0, C.byref(res), _ptr(charge),
+                                     _ptr(U), _ptr(tr))
+        if st == NEGF_PENDING:
+            return None
+        _check(st)
+        self._sizes.pop(rid, None)
+        return dict(status=res.status, iterations=res.iterations, eps_max=res.eps_max, current=res.current,
+                    t_queue_ms=res.t_queue_ms, t_run_ms=res.t_run_ms, t_total_ms=res.t_total_ms, charge=charge,
+                    U=U, trace=tr[:res.iterations].copy())
+
+    def stats(self) -> dict:
+        info = negf_server_info()
+        st = load().negf_server_stats(self.h, C.byref(info))
+        return dict(status=st, pending=info.pending, running=info.running, passes=info.passes,
+                    hbm_used=info.hbm_used, hbm_budget=info.hbm_budget, workspace_bytes=info.workspace_bytes)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().negf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

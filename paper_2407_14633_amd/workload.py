@@ -337,3 +337,106 @@ def batch_problems(n_dev: int = 64, seed: int = 4040, chiralities=(10, 13, 17, 2
         n_c = int(round(contour_frac * ne))
         out.append(device_problem(N=N, n=n, seed=int(seed * 1000 + k), n_c=n_c, n_r=ne - n_c, V=V))
     return out
+
+
+# --------------------------------------------------------------------------
+# Self-consistent bias points (serving requests)
+# --------------------------------------------------------------------------
+EPS0 = 8.8541878128e-12      # F/m
+RING_SPACING = 0.1065e-9     # m, mean axial ring spacing of a zigzag tube (Table 1 mesh spacing)
+LATTICE_A = 0.246e-9         # m, graphene lattice constant
+
+
+@dataclass
+class Electrostatics:
+    """1-D finite-difference Poisson along the tube axis with a coaxial gate.
+
+    Per ring j (potential phi_j in V, extra electrons rho_j - n_ref_j):
+      -(eps_1d/dz^2)(phi_{j+1} - 2 phi_j + phi_{j-1}) + c_gate (phi_j - V_GS)
+          = -e (rho_j - n_ref_j) / dz,
+    phi_{-1} = 0 (source), phi_N = V_DS (drain); electron potential energy U_j = -phi_j (eV).
+    """
+    dz: float                 # m
+    eps_1d: float             # F m
+    c_gate: float             # F/m
+    n_ref: np.ndarray         # (N,) electrons per ring of the neutral tube
+    V_DS: float               # V
+    V_GS: float               # V
+
+
+@dataclass
+class ScRequest:
+    """One self-consistent bias point: device, grid, electrostatics, mixing settings."""
+    name: str
+    device: Device
+    bias: Bias                # mu_L = source level, mu_R = mu_L - V_DS
+    grid: EnergyGrid
+    elec: Electrostatics
+    eta: float = 1e-6
+    decim_tol: float = 1e-12
+    decim_max_iter: int = 64
+    g_s: float = 2.0
+    zeta: float = 0.1         # Broyden fraction
+    tol: float = 1e-5         # stop when max_j |f_j / (rho_in_j + rho_out_j)| < tol
+    history: int = 8
+    max_iter: int = 100
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def U_left(self) -> float:
+        return 0.0
+
+    @property
+    def U_right(self) -> float:
+        return -self.elec.V_DS
+
+
+def cnt_electrostatics(n: int, N: int, V_DS: float, V_GS: float, kappa: float = 3.9,
+                       t_ox: float = 10e-9) -> Electrostatics:
+    """Coaxial gate around an (n,0) tube: r = d/2, d = a n / pi; c_gate = 2 pi eps0 kappa /
+    ln((r + t_ox)/r); eps_1d = eps0 kappa pi ((r + t_ox)^2 - r^2) (axial flux through the
+    oxide annulus); one electron per atom in the neutral tube."""
+    r = 0.5 * LATTICE_A * n / np.pi
+    c_gate = 2.0 * np.pi * EPS0 * kappa / np.log((r + t_ox) / r)
+    eps_1d = EPS0 * kappa * np.pi * ((r + t_ox) ** 2 - r ** 2)
+    return Electrostatics(RING_SPACING, float(eps_1d), float(c_gate), np.full(N, float(n)), float(V_DS),
+                          float(V_GS))
+
+
+def sc_request(n: int, N: int, V_DS: float, V_GS: float, n_c: int, n_r: int, mu_S: float = 0.0,
+               name: Optional[str] = None, **kw) -> ScRequest:
+    """A flat zigzag tube at a bias point; the contour starts well below any band
+    the gate or drain can pull down."""
+    dev = zigzag_cnt(n, N)
+    bias = Bias(mu_L=mu_S, mu_R=mu_S - V_DS)
+    E_b = -3.0 * abs(T_CC) - abs(V_DS) - abs(V_GS) - 1.0
+    grid = nonequilibrium_grid(E_b, bias, n_c, n_r)
+    return ScRequest(name or f"sc_cnt{n}_N{N}_Vds{V_DS:.3f}_Vgs{V_GS:.3f}", dev, bias, grid,
+                     cnt_electrostatics(n, N, V_DS, V_GS), meta=dict(n=n, N=N), **kw)
+
+
+def serving_requests(n_req: int, seed: int = 5555, chiralities=(10, 13, 17, 20, 23), N_range=(200, 2000),
+                     ne_range=(512, 4096), contour_frac: float = 0.25, eta: float = 1e-3, **kw) -> list:
+    """Requests drawn like the batching workload, with V_DS ~ U[0, 0.6] and V_GS ~ U[-0.5, 0.5].
+
+    eta = 1e-3 eV: with a few thousand fixed real-axis nodes, resonances of
+    linewidth 1e-6 eV in long channels are not resolved, the computed charge then
+    jumps as the potential moves them across nodes, and the mixing stalls near
+    1e-4; a 1e-3 eV broadening makes the charge a smooth function of U."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_req):
+        n = int(rng.choice(chiralities))
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        ne = int(rng.integers(ne_range[0], ne_range[1] + 1))
+        n_c = int(round(contour_frac * ne))
+        V_DS = float(rng.uniform(0.0, 0.6))
+        V_GS = float(rng.uniform(-0.5, 0.5))
+        out.append(sc_request(n, N, V_DS, V_GS, n_c, ne - n_c, eta=eta, **kw))
+    return out
+
+
+def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream of `rate` requests per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
