@@ -78,7 +78,7 @@ def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
     return {"recur": recur, "cdiag": cdiag, "column": column, "decimate": dec}
 
 
-def cpu_baseline(p: W.Problem, n_c: int = 8, n_r: int = 24, seed: int = 99) -> dict:
+def cpu_baseline(p: W.Problem, n_c: int = 16, n_r: int = 48, seed: int = 99) -> dict:
     """The oracle as it stands, timed on the host cores over a fixed sample of nodes."""
     from concurrent.futures import ProcessPoolExecutor
     cores = min(os.cpu_count() or 1, 16, n_c + n_r)
@@ -341,7 +341,7 @@ def main():
     ap.add_argument("--workload", default="device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--requests", type=int, default=16, help="serving: number of requests")
+    ap.add_argument("--requests", type=int, default=8, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=10.0, help="serving: Poisson arrival rate (req/s)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-fp32", action="store_true", help="serving: FP32-bulk NEGF instead of FP64")
@@ -388,6 +388,10 @@ def main():
         fp32 = {"value": n_e / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
                 "roofline": rf32, "charge_rel_diff_vs_fp64": err,
                 "current_rel_diff_vs_fp64": abs(r32["current"] - r64["current"]) / abs(r64["current"] or 1.0)}
+    serving = None
+    if not a.no_serving:
+        serving = run_serving(a.requests, a.rate)
+        log("serving", serving)
     line = {
         "metric": METRIC, "value": n_e / (r64["ms_per_step"] * 1e-3), "unit": "energy-point solves/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r64["ms_per_step"],
@@ -398,7 +402,7 @@ def main():
                    "n_real": p.grid.n_r},
         "roofline": rf64, "cpu_baseline": cpu, "fp32_bulk": fp32,
         "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in r64["times"].items()},
-        "serving": None,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

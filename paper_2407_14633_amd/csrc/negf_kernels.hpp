@@ -732,13 +732,14 @@ __device__ __forceinline__ void gs_row(cx<double>* M, int r, const double (&xr)[
     for (int j = 0; j < B; ++j) M[r * B + j] = cx<double>{xr[j], xi[j]};
 }
 
-// out = x * Y for a B x B block Y inside an LDS matrix of row stride LD
+// out = x * Y for a B x B block Y inside an LDS matrix of row stride LD (unrolled:
+// x lives in registers and may only be indexed by compile-time constants)
 template <int B, int LD>
 __device__ __forceinline__ void row_mul_ld(const double (&xr)[B], const double (&xi)[B], const cx<double>* Y,
                                            double (&orr)[B], double (&oi)[B]) {
 #pragma unroll
     for (int j = 0; j < B; ++j) { orr[j] = 0.0; oi[j] = 0.0; }
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < B; ++k) {
         const double a = xr[k], b = xi[k];
 #pragma unroll
@@ -958,6 +959,7 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
         wave_sync();
 
         // row q of z - eps, eps = [[e, V],[V^H, e']] with the e row in (er, ei)
+        // (register indices stay compile-time constants: the halves are selected by value)
         auto layer_row = [&](double (&mr)[BB], double (&mi)[BB]) {
 #pragma unroll
             for (int j = 0; j < BB; ++j) { mr[j] = 0.0; mi[j] = 0.0; }
@@ -966,12 +968,12 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     const cx<double> c = cpl[j];
-                    const int jd = top ? j : B + j;      // diagonal block column
-                    const int jc = top ? B + j : j;      // coupling block column
-                    mr[jd] = (j == i ? z.re : 0.0) - er[j];
-                    mi[jd] = (j == i ? z.im : 0.0) - ei[j];
-                    mr[jc] = -c.re;
-                    mi[jc] = -c.im;
+                    const double dre = (j == i ? z.re : 0.0) - er[j];   // diagonal block entry
+                    const double dim = (j == i ? z.im : 0.0) - ei[j];
+                    mr[j] = top ? dre : -c.re;
+                    mi[j] = top ? dim : -c.im;
+                    mr[B + j] = top ? -c.re : dre;
+                    mi[B + j] = top ? -c.im : dim;
                 }
             }
         };
