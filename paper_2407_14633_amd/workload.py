@@ -440,3 +440,48 @@ def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson stream of `rate` requests per second."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+# --------------------------------------------------------------------------
+# Equilibrium grids
+# --------------------------------------------------------------------------
+def equilibrium_grid(E_b: float, mu: float, kT: float, n_arc: int, n_line: int, n_poles: int = 8,
+                     start: float = 10.0, end: float = 40.0) -> tuple[EnergyGrid, int]:
+    """Contour for the equilibrium density with Fermi-pole residues.
+
+    The path leaves E_b on a circle centred on the real axis, reaches
+    P = (mu - start kT) + i delta with delta = 2 n_poles pi kT (half-way between the
+    n_poles-th and the next pole of F), and runs horizontally to (mu + end kT) + i delta.
+    On that line F(z - mu) equals the real Fermi function of Re z, so both pieces
+    are smooth; the n_poles poles below the line are returned for the residue sum.
+    Nodes are Gauss-Legendre on each piece; weights include dz/dt."""
+    delta = 2.0 * n_poles * np.pi * kT
+    xp = mu - start * kT
+    c = (xp * xp + delta * delta - E_b * E_b) / (2.0 * (xp - E_b))
+    R = c - E_b
+    th_p = np.arctan2(delta, xp - c)
+    x, w = gauss_legendre(n_arc)
+    t = 0.5 * (x + 1.0)
+    th = np.pi + (th_p - np.pi) * t
+    z_a = c + R * np.exp(1j * th)
+    w_a = 1j * R * np.exp(1j * th) * (th_p - np.pi) * 0.5 * w
+    x, w = gauss_legendre(n_line)
+    t = 0.5 * (x + 1.0)
+    x_end = mu + end * kT
+    z_l = xp + 1j * delta + t * (x_end - xp)
+    w_l = (x_end - xp) * 0.5 * w + 0j
+    grid = EnergyGrid(np.concatenate([z_a, z_l]).astype(np.complex128),
+                      np.concatenate([w_a, w_l]).astype(np.complex128), np.zeros(0), np.zeros(0))
+    return grid, int(n_poles)
+
+
+def neutral_grid(E_b: float, n_c: int) -> EnergyGrid:
+    """Arc from E_b to 0 (the reference density rho_0 integrates up to E = 0)."""
+    z_c, w_c = semicircle_contour(E_b, 0.0, n_c)
+    return EnergyGrid(z_c, w_c, np.zeros(0), np.zeros(0))
+
+
+def conductance_grid(mu: float, kT: float, n_r: int, tail: float = FERMI_TAIL) -> EnergyGrid:
+    """Gauss-Legendre real-axis nodes on [mu - f kT, mu + f kT] for Eq. 6."""
+    E_r, w_r = real_axis_gl(mu - tail * kT, mu + tail * kT, n_r)
+    return EnergyGrid(np.zeros(0, np.complex128), np.zeros(0, np.complex128), E_r, w_r)
