@@ -195,6 +195,17 @@ typedef struct {
                                   2: reuse sigma_cache, no decimation (valid while the
                                      nodes, eta and the lead potentials are unchanged,
                                      Eq. 2: Sigma depends on nothing else)            */
+    /* Equilibrium density and conductance (text after Eq. 4; Eq. 6): */
+    int n_poles;               /* residue nodes mu_min + i(2k+1) pi kT_min, k < n_poles,
+                                  added after the contour nodes with weight
+                                  -2 pi i kT_min and no Fermi factor: the poles of F
+                                  enclosed between the contour and the real axis     */
+    int contour_no_fermi;      /* 1: contour weights used as given (no F): the
+                                  zero-temperature arc of the reference density     */
+    double *conductance;       /* [1] output or NULL: g_s (e^2/h) sum_r w_r T(E_r)
+                                  (-dF/dE)(E_r - mu_L; kT_L), A/V (Eq. 6)            */
+    /* sigma_cache, when used, and every per-node quantity cover n_c + n_poles + n_r
+       nodes in that order. */
 } negf_job;
 
 /* Workspace for batches: recursion stores, per-node arrays and the job/span

@@ -121,8 +121,10 @@ negf_status check_job(const negf_job& j, int idx, bool host) {
         return fail(NEGF_EINVAL, "job %d: bias needs finite mu and kT > 0", idx);
     if (j.n_c < 0 || j.n_r < 0)
         return fail(NEGF_EINVAL, "job %d: negative node count (n_c=%d, n_r=%d)", idx, j.n_c, j.n_r);
-    if (j.n_c + j.n_r < 1) return fail(NEGF_EINVAL, "job %d: no energy nodes", idx);
-    if ((long long)j.n_c + j.n_r > (1LL << 26)) return fail(NEGF_EINVAL, "job %d: too many energy nodes", idx);
+    if (j.n_poles < 0 || j.n_poles > (1 << 20)) return fail(NEGF_EINVAL, "job %d: n_poles = %d", idx, j.n_poles);
+    if (j.n_c + j.n_poles + j.n_r < 1) return fail(NEGF_EINVAL, "job %d: no energy nodes", idx);
+    if ((long long)j.n_c + j.n_poles + j.n_r > (1LL << 26))
+        return fail(NEGF_EINVAL, "job %d: too many energy nodes", idx);
     if (j.n_c > 0 && (!j.z_c || !j.w_c)) return fail(NEGF_EINVAL, "job %d: contour nodes/weights are NULL", idx);
     if (j.n_r > 0 && (!j.E_r || !j.w_r)) return fail(NEGF_EINVAL, "job %d: real-axis nodes/weights are NULL", idx);
     if (!j.charge) return fail(NEGF_EINVAL, "job %d: charge output is NULL", idx);
@@ -192,7 +194,8 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     w->last_max_iter.assign(n_jobs, 0);
     for (int i = 0; i < n_jobs; ++i) {
         negf_device* d = jobs[i].dev;
-        const int ne = jobs[i].n_c + jobs[i].n_r;
+        const int ncz = jobs[i].n_c + jobs[i].n_poles;   // contour-type nodes: given + poles
+        const int ne = ncz + jobs[i].n_r;
         const size_t Nb = (size_t)d->N * d->b, b2 = (size_t)d->b * d->b;
         JobPlan& p = plan[i];
         p.d = d;
@@ -204,7 +207,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         size_t& ad = d->opt.precision == NEGF_FP32_BULK ? ad32 : ad64;
         p.o_gr = gr;
         p.o_ad = ad;
-        gr += (size_t)jobs[i].n_c * Nb;
+        gr += (size_t)ncz * Nb;
         ad += (size_t)jobs[i].n_r * 2 * Nb;
         nodes += ne;
         sig += (size_t)ne * 2 * b2;
@@ -218,7 +221,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     TRY(grow(w, w->iters, nodes * 2 * 4));
     TRY(grow(w, w->status, nodes * 4));
     TRY(grow(w, w->coef_c, nodes * 16));
-    TRY(grow(w, w->coef_r, nodes * 3 * 8));
+    TRY(grow(w, w->coef_r, nodes * 4 * 8));
     TRY(grow(w, w->T, nodes * 8));
     TRY(grow(w, w->gr, gr64 * 16 + gr32 * 8));   // FP64 jobs first, FP32 jobs behind them
     TRY(grow(w, w->ad, ad64 * 8 + ad32 * 4));
@@ -245,7 +248,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         const bool f32 = d->opt.precision == NEGF_FP32_BULK;
         negf::JobDesc& D = jd[i];
         D.N = d->N;
-        D.n_c = J.n_c;
+        D.n_c = J.n_c + J.n_poles;
         D.n_r = J.n_r;
         D.K = d->K;
         D.n_uniq = d->n_uniq;
@@ -275,7 +278,11 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         }
         negf::RedJob& R = rj[i];
         R.Nb = d->N * d->b;
-        R.n_c = J.n_c;
+        R.n_c = J.n_c + J.n_poles;
+        R.n_ci = J.n_c;
+        R.n_p = J.n_poles;
+        R.no_fermi = J.contour_no_fermi ? 1 : 0;
+        R.conductance = J.conductance;
         R.n_r = J.n_r;
         R.g_s = d->opt.g_s;
         R.eta = d->opt.eta;
@@ -289,7 +296,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         R.w_r = J.w_r;
         R.z = static_cast<cx<double>*>(w->z.p) + p.o_node;
         R.coef_c = static_cast<cx<double>*>(w->coef_c.p) + p.o_node;
-        R.coef_r = static_cast<double*>(w->coef_r.p) + 3 * p.o_node;
+        R.coef_r = static_cast<double*>(w->coef_r.p) + 4 * p.o_node;
         R.gr_diag = D.gr_diag;
         R.a_diag = D.a_diag;
         R.T = D.Tout;
@@ -600,7 +607,7 @@ negf_status solve_host(negf_workspace* w, int n_jobs, const negf_job* jobs, cons
     TRY(grow(w, w->in_wr, nr * 8));
     TRY(grow(w, w->out_charge, nb * 8));
     TRY(grow(w, w->out_T, nr * 8));
-    TRY(grow(w, w->out_cur, (size_t)n_jobs * 8));
+    TRY(grow(w, w->out_cur, (size_t)n_jobs * 2 * 8));   // current, conductance
     hipStream_t s = w->own_stream;
     std::vector<negf_job> dj(jobs, jobs + n_jobs);
     size_t oc = 0, orr = 0, ob = 0;
@@ -624,7 +631,8 @@ negf_status solve_host(negf_workspace* w, int n_jobs, const negf_job* jobs, cons
         j.w_r = wr;
         j.charge = static_cast<double*>(w->out_charge.p) + ob;
         j.T = static_cast<double*>(w->out_T.p) + orr;
-        j.current = static_cast<double*>(w->out_cur.p) + i;
+        j.current = static_cast<double*>(w->out_cur.p) + 2 * i;
+        j.conductance = jobs[i].conductance ? static_cast<double*>(w->out_cur.p) + 2 * i + 1 : nullptr;
         oc += j.n_c;
         orr += j.n_r;
         ob += (size_t)j.dev->N * j.dev->b;
@@ -639,6 +647,7 @@ negf_status solve_host(negf_workspace* w, int n_jobs, const negf_job* jobs, cons
         HIPCHK(hipMemcpy(jobs[i].charge, j.charge, Nb * 8, hipMemcpyDeviceToHost));
         if (jobs[i].T && j.n_r) HIPCHK(hipMemcpy(jobs[i].T, j.T, (size_t)j.n_r * 8, hipMemcpyDeviceToHost));
         if (jobs[i].current) HIPCHK(hipMemcpy(jobs[i].current, j.current, 8, hipMemcpyDeviceToHost));
+        if (jobs[i].conductance) HIPCHK(hipMemcpy(jobs[i].conductance, j.conductance, 8, hipMemcpyDeviceToHost));
     }
     if (outs) {   // with one job, its arrays start at offset 0 of their buffers
         negf_device* d = dj[0].dev;

@@ -67,7 +67,8 @@ class negf_job(C.Structure):
     _fields_ = [("dev", C.c_void_p), ("bias", negf_bias), ("n_c", C.c_int), ("z_c", C.c_void_p),
                 ("w_c", C.c_void_p), ("n_r", C.c_int), ("E_r", C.c_void_p), ("w_r", C.c_void_p),
                 ("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p),
-                ("sigma_cache", C.c_void_p), ("sigma_mode", C.c_int)]
+                ("sigma_cache", C.c_void_p), ("sigma_mode", C.c_int), ("n_poles", C.c_int),
+                ("contour_no_fermi", C.c_int), ("conductance", C.c_void_p)]
 
 
 class negf_schedule(C.Structure):
@@ -194,6 +195,7 @@ class SolveResult:
     al_diag: Optional[np.ndarray] = None
     ar_diag: Optional[np.ndarray] = None
     decim_iters: Optional[np.ndarray] = None
+    conductance: Optional[float] = None
 
 
 class NegfDevice:
@@ -307,10 +309,14 @@ def _kernel_times(fn, h) -> dict:
 
 @dataclass
 class Job:
-    """One entry of a batch: a device handle, its bias and its energy grid."""
+    """One entry of a batch: a device handle, its bias and its energy grid (optionally
+    with Fermi-pole residue nodes, a zero-temperature contour, and Eq. 6)."""
     dev: NegfDevice
     bias: Bias
     grid: EnergyGrid
+    n_poles: int = 0
+    contour_no_fermi: bool = False
+    conductance: bool = False
 
 
 class Workspace:
@@ -357,17 +363,20 @@ class Workspace:
             g = jb.grid
             zc, wc = _c(g.z_c, np.complex128), _c(g.w_c, np.complex128)
             Er, wr = _c(g.E_r, np.float64), _c(g.w_r, np.float64)
-            charge, T, cur = np.zeros(jb.dev.N * jb.dev.b), np.zeros(Er.shape[0]), np.zeros(1)
+            charge, T, cur, cond = np.zeros(jb.dev.N * jb.dev.b), np.zeros(Er.shape[0]), np.zeros(1), np.zeros(1)
             keep += [zc, wc, Er, wr]
             arr[k] = negf_job(jb.dev.h, negf_bias(jb.bias.mu_L, jb.bias.mu_R, jb.bias.kT_L, jb.bias.kT_R),
                               zc.shape[0], _ptr(zc), _ptr(wc), Er.shape[0], _ptr(Er), _ptr(wr), _ptr(charge),
-                              _ptr(T), _ptr(cur))
+                              _ptr(T), _ptr(cur), None, 0, int(jb.n_poles), int(bool(jb.contour_no_fermi)),
+                              _ptr(cond) if jb.conductance else None)
             res.append(SolveResult(charge, T, 0.0))
             res[-1]._cur = cur
+            res[-1]._cond = cond if jb.conductance else None
         _check(load().negf_batch_solve(self.h, len(jobs), arr))
         for r in res:
             r.current = float(r._cur[0])
-            del r._cur
+            r.conductance = None if r._cond is None else float(r._cond[0])
+            del r._cur, r._cond
         return res
 
     def solve_dev(self, jobs, stream=None):
