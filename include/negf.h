@@ -261,6 +261,29 @@ negf_status negf_graph_launch(negf_graph *g, void *hip_stream);
 negf_status negf_graph_sync(negf_graph *g, int *failed_job);
 void negf_graph_destroy(negf_graph *g);
 
+/* --------------------------------------------------------- mode space ----
+ * Section 2.1 and Section 2.2.3: a tube in the mode-space representation, one
+ * scalar chain per ring mode.  Every ring block (h_diag, h_up, lead blocks, tau)
+ * must be circulant, H[i][j] = H[0][(j - i) mod b], and the potential uniform on
+ * each ring; then mode q sees the scalar lambda_q(C) = sum_k C[0][k] e^{2 pi i qk/b}
+ * of every block C and the b modes decouple exactly.  n_modes = 0 keeps all b
+ * modes (exact); otherwise modes[n_modes] lists the kept ones (the mode-space
+ * approximation: charge and current of those modes only).  A solve runs the kept
+ * modes as one batch on workspace w; per-atom charge is (1/b) sum_q charge_q of
+ * the atom's ring, T and current add over modes.  EINVAL if a block is not
+ * circulant.  Host pointers, synchronous. */
+typedef struct negf_modes negf_modes;
+negf_status negf_modes_create(negf_modes **out, int n_rings, int b, const negf_c64 *h_diag, const negf_c64 *h_up,
+                              const negf_lead *left, const negf_lead *right, const negf_options *opt,
+                              int n_modes, const int *modes);
+/* U_ring[n_rings]: on-site potential energy of every atom of ring j (eV). */
+negf_status negf_modes_set_potential(negf_modes *m, const double *U_ring, double U_left, double U_right);
+negf_status negf_modes_solve(negf_modes *m, negf_workspace *w, const negf_bias *bias,
+                             int n_c, const negf_c64 *z_c, const negf_c64 *w_c,
+                             int n_r, const double *E_r, const double *w_r,
+                             double *charge, double *T, double *current);
+void negf_modes_destroy(negf_modes *m);
+
 /* ------------------------------------------------------------ serving ----
  * Self-consistent bias points (Section 2.4, Algorithm 3) served with continuous
  * batching.  A request is a device with flat leads, a bias point and a fixed

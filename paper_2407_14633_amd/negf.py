@@ -31,7 +31,8 @@ EXPORTED = [
     "negf_workspace_kernel_times", "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev",
     "negf_batch_sync", "negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create",
     "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy", "negf_server_create", "negf_server_submit",
-    "negf_server_poll", "negf_server_stats", "negf_server_destroy",
+    "negf_server_poll", "negf_server_stats", "negf_server_destroy", "negf_modes_create",
+    "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy",
 ]
 
 
@@ -145,6 +146,14 @@ def load(path: str = LIB_PATH):
     lib.negf_graph_sync.argtypes = [vp, C.POINTER(i)]
     lib.negf_graph_destroy.argtypes = [vp]
     lib.negf_graph_destroy.restype = None
+    lib.negf_modes_create.argtypes = [C.POINTER(vp), i, i, vp, vp, C.POINTER(negf_lead), C.POINTER(negf_lead),
+                                      C.POINTER(negf_options), i, vp]
+    lib.negf_modes_set_potential.argtypes = [vp, vp, d, d]
+    lib.negf_modes_solve.argtypes = [vp, vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp]
+    lib.negf_modes_destroy.argtypes = [vp]
+    lib.negf_modes_destroy.restype = None
+    for name in ("negf_modes_create", "negf_modes_set_potential", "negf_modes_solve"):
+        getattr(lib, name).restype = C.c_int
     lib.negf_server_create.argtypes = [C.POINTER(vp), sz, i, sz]
     lib.negf_server_submit.argtypes = [vp, C.POINTER(negf_sc_request), C.POINTER(C.c_longlong)]
     lib.negf_server_poll.argtypes = [vp, C.c_longlong, i, C.POINTER(negf_sc_result), vp, vp, vp]
@@ -545,6 +554,62 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             load().negf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class ModeSpace:
+    """negf_modes: a ring-circulant tube as independent scalar mode chains."""
+
+    def __init__(self, dev: Device, modes=None, precision: int = FP64, eta: float = 1e-6,
+                 decim_tol: float = 1e-12, decim_max_iter: int = 64, g_s: float = 2.0):
+        self.N, self.b = dev.n_rings, dev.b
+        keep = []
+
+        def arr(a):
+            a = _c(a, np.complex128)
+            keep.append(a)
+            return _ptr(a)
+
+        leads = [negf_lead(ld.period, arr(ld.h_diag), arr(ld.h_up), arr(ld.tau)) for ld in (dev.left, dev.right)]
+        o = default_options()
+        o.precision, o.eta, o.decim_tol, o.decim_max_iter, o.g_s = precision, eta, decim_tol, decim_max_iter, g_s
+        ml = None if modes is None else _c(modes, np.int32)
+        h = C.c_void_p()
+        _check(load().negf_modes_create(C.byref(h), self.N, self.b, arr(dev.h_diag),
+                                        arr(dev.h_up) if self.N > 1 else None, C.byref(leads[0]), C.byref(leads[1]),
+                                        C.byref(o), 0 if ml is None else int(ml.shape[0]), _ptr(ml)))
+        self.h = h
+
+    def set_potential(self, U_ring, U_left: float = 0.0, U_right: float = 0.0):
+        U = _c(U_ring, np.float64)
+        if U.shape != (self.N,):
+            raise ValueError(f"U_ring must have shape ({self.N},)")
+        _check(load().negf_modes_set_potential(self.h, _ptr(U), float(U_left), float(U_right)))
+
+    def solve(self, ws: "Workspace", bias: Bias, grid: EnergyGrid) -> SolveResult:
+        zc, wc = _c(grid.z_c, np.complex128), _c(grid.w_c, np.complex128)
+        Er, wr = _c(grid.E_r, np.float64), _c(grid.w_r, np.float64)
+        charge, T, cur = np.zeros(self.N * self.b), np.zeros(Er.shape[0]), np.zeros(1)
+        b = negf_bias(bias.mu_L, bias.mu_R, bias.kT_L, bias.kT_R)
+        _check(load().negf_modes_solve(self.h, ws.h, C.byref(b), zc.shape[0], _ptr(zc), _ptr(wc), Er.shape[0],
+                                       _ptr(Er), _ptr(wr), _ptr(charge), _ptr(T), _ptr(cur)))
+        return SolveResult(charge, T, float(cur[0]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().negf_modes_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,76 @@
+"""Mode-space solves: every ring block of a zigzag tube is circulant, so with a
+ring-uniform potential the ring Fourier modes decouple into scalar chains.  With
+all modes kept the charge, T(E) and current must equal the real-space result."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import negf_oracle as O
+from paper_2407_14633_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("n,N", [(8, 24), (10, 30), (13, 17)])
+def test_all_modes_equal_real_space_oracle(gpu_lib, n, N):
+    negf = gpu_lib
+    dev = W.zigzag_cnt(n, N)
+    U = W.potential_smooth_ring(N, n, 0.25, 11)           # uniform on every ring
+    bias = W.Bias(0.1, -0.1)
+    grid = W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 16, 40)
+    p = W.Problem("ms", dev, U, 0.0, 0.0, bias, grid)
+    ref = O.solve(p)
+    with negf.ModeSpace(dev) as ms, negf.Workspace() as ws:
+        ms.set_potential(U[::n])
+        got = ms.solve(ws, bias, grid)
+    dI = abs(got.current - ref["current"]) / abs(ref["current"])
+    say(f"  ({n},0) N={N}: charge {rel(got.charge, ref['charge']):.2e} T {rel(got.T, ref['T']):.2e} current {dI:.2e}")
+    assert rel(got.charge, ref["charge"]) < 1e-10
+    assert rel(got.T, ref["T"]) < 1e-9
+    assert dI < 1e-9
+
+
+def test_modes_match_real_space_gpu_at_device_scale(gpu_lib):
+    negf = gpu_lib
+    N, n = 400, 17
+    dev = W.zigzag_cnt(n, N)
+    j = np.arange(N)
+    prof = 0.15 * (np.tanh((j - N / 4) / 10) - np.tanh((j - 3 * N / 4) / 10))
+    U = np.repeat(prof, n)
+    bias = W.Bias(0.15, -0.15)
+    grid = W.subsample_grid(W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 512, 1536), 24, 48, 3)
+    with negf.NegfDevice(dev) as d:
+        d.set_potential(U)
+        real = d.solve(bias, grid)
+    with negf.ModeSpace(dev) as ms, negf.Workspace() as ws:
+        ms.set_potential(prof)
+        got = ms.solve(ws, bias, grid)
+        # the mode-space approximation: only the two lowest (degenerate) subbands
+        two = negf.ModeSpace(dev, modes=[6, 11])
+        two.set_potential(prof)
+        low = two.solve(ws, bias, grid)
+        two.close()
+    dI = abs(got.current - real.current) / abs(real.current)
+    dI2 = abs(low.current - real.current) / abs(real.current)
+    say(f"  (17,0) N=400 all modes: charge {rel(got.charge, real.charge):.2e} current {dI:.2e}; "
+        f"two lowest modes: current {dI2:.2e}")
+    assert rel(got.charge, real.charge) < 1e-10 and dI < 1e-9
+    assert dI2 < 1e-2
+
+
+def test_non_circulant_device_is_refused(gpu_lib):
+    negf = gpu_lib
+    dev = W.random_device(4, 3, seed=5)
+    with pytest.raises(negf.NegfError) as ei:
+        negf.ModeSpace(dev)
+    assert ei.value.status == negf.NEGF_EINVAL
