@@ -261,6 +261,22 @@ negf_status negf_graph_launch(negf_graph *g, void *hip_stream);
 negf_status negf_graph_sync(negf_graph *g, int *failed_job);
 void negf_graph_destroy(negf_graph *g);
 
+/* ------------------------------------------------ semi-adaptive grid ----
+ * Section 4 (number of integration points): the real-axis window [E_min, E_max]
+ * (Eq. 4, f1 = f2 = 14) is split at E_l1 < E_l2 into three parts, each integrated
+ * by Gauss-Legendre with density[p] nodes per kT_min (at least one node).  The
+ * integrand f_L A_L + f_R A_R summed over the atoms of ring N/2 is evaluated on
+ * the grid of the guessed limits by a real-axis solve of d (at its current
+ * potential), its peak E_s located, and the limits refined as
+ *     E_l1 <- E_l1 - a kT_min,  E_l2 <- E_s + b kT_min
+ * (clipped to the window and kept ordered; the paper uses a = 3, b = 1).  The
+ * refined grid is written to E_r/w_r (host arrays of capacity cap); *n_r always
+ * receives its size and limits[3] (if not NULL) = {E_l1, E_l2, E_s}.  EINVAL if
+ * cap is too small (call again with *n_r). */
+negf_status negf_semi_adaptive_grid(negf_device *d, const negf_bias *bias, double E_l1, double E_l2,
+                                    double a, double b, const double *density,
+                                    double *E_r, double *w_r, int cap, int *n_r, double *limits);
+
 /* --------------------------------------------------------- mode space ----
  * Section 2.1 and Section 2.2.3: a tube in the mode-space representation, one
  * scalar chain per ring mode.  Every ring block (h_diag, h_up, lead blocks, tau)

@@ -32,7 +32,7 @@ EXPORTED = [
     "negf_batch_sync", "negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create",
     "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy", "negf_server_create", "negf_server_submit",
     "negf_server_poll", "negf_server_stats", "negf_server_destroy", "negf_modes_create",
-    "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy",
+    "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy", "negf_semi_adaptive_grid",
 ]
 
 
@@ -150,6 +150,8 @@ def load(path: str = LIB_PATH):
                                       C.POINTER(negf_options), i, vp]
     lib.negf_modes_set_potential.argtypes = [vp, vp, d, d]
     lib.negf_modes_solve.argtypes = [vp, vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp]
+    lib.negf_semi_adaptive_grid.argtypes = [vp, C.POINTER(negf_bias), d, d, d, d, vp, vp, vp, i, C.POINTER(i), vp]
+    lib.negf_semi_adaptive_grid.restype = C.c_int
     lib.negf_modes_destroy.argtypes = [vp]
     lib.negf_modes_destroy.restype = None
     for name in ("negf_modes_create", "negf_modes_set_potential", "negf_modes_solve"):
@@ -305,6 +307,20 @@ class NegfDevice:
 
     def device_bytes(self) -> int:
         return int(load().negf_device_bytes(self.h))
+
+    def semi_adaptive_grid(self, bias: Bias, E_l1: float, E_l2: float, density, a: float = 3.0, b: float = 1.0):
+        """Refined three-part real-axis grid: (E_r, w_r, (E_l1, E_l2, E_s))."""
+        dens = _c(density, np.float64)
+        bb = negf_bias(bias.mu_L, bias.mu_R, bias.kT_L, bias.kT_R)
+        n = C.c_int(0)
+        lim = np.zeros(3)
+        # capacity: every part at the largest density over the whole window, plus one node per part
+        width = abs(bias.mu_L - bias.mu_R) + 28.0 * max(bias.kT_L, bias.kT_R)
+        cap = int(np.ceil(float(np.max(dens)) * width / min(bias.kT_L, bias.kT_R))) + 3
+        E, w = np.zeros(cap), np.zeros(cap)
+        _check(load().negf_semi_adaptive_grid(self.h, C.byref(bb), E_l1, E_l2, a, b, _ptr(dens), _ptr(E), _ptr(w),
+                                              cap, C.byref(n), _ptr(lim)))
+        return E[:n.value].copy(), w[:n.value].copy(), tuple(lim)
 
 
 def _kernel_times(fn, h) -> dict:
