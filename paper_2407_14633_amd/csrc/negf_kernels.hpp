@@ -31,6 +31,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Resident waves per SIMD the recursion kernels are compiled for (register budget).
+#ifndef NEGF_RGF_WAVES
+#define NEGF_RGF_WAVES 2
+#endif
+
 namespace negf {
 
 template <typename T> struct cx { T re, im; };
@@ -105,7 +110,9 @@ __device__ __forceinline__ void gj_inverse(T (&ar)[B], T (&ai)[B], const Grp<T, 
     T sr = T(1), si = T(0);   // deferred row scale
     if (!used) atomicMax(&g.keys[0], pivot_key(ar[0], ai[0], g.r));
     wave_sync();
-#pragma unroll
+    // fully unrolled for every block size used (up to 48 rows): the register rows may
+    // only be indexed by compile-time constants
+#pragma clang loop unroll(full)
     for (int k = 0; k < B; ++k) {
         const int p = key_row(g.keys[k], B);
         const bool piv = g.act && (g.r == p);
@@ -372,7 +379,7 @@ __device__ __forceinline__ void invert_fp64_into(const JobDesc& J, int e, int n,
 }
 
 template <typename T, int B>
-__global__ __launch_bounds__(64, 2) void k_recur(Sched S) {
+__global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_recur(Sched S) {
     constexpr int G = 64 / B;
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr int G64 = kF32 ? G : 1;   // FP64 boundary buffers (FP32-bulk form only)
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(64, 2) void k_recur(Sched S) {
 // ================================================================ k_cdiag ==
 // Item = (contour node, ring n): G_nn = (a_n - x_n - y_n)^{-1}, diagonal kept.
 template <typename T, int B>
-__global__ __launch_bounds__(64, 2) void k_cdiag(Sched S) {
+__global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_cdiag(Sched S) {
     constexpr int G = 64 / B;
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr int G64 = kF32 ? G : 1;
@@ -595,7 +602,7 @@ __global__ __launch_bounds__(64, 2) void k_cdiag(Sched S) {
 // Each ring's diag(W Gamma W^H) is written; the right chain ends with
 // T_LR = Tr[Gamma_L W_0 Gamma_R W_0^H] (Eq. 5).
 template <typename T, int B>
-__global__ __launch_bounds__(64, 2) void k_column(Sched S) {
+__global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_gam[G][B * B];
@@ -916,6 +923,7 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
     constexpr int BB = 2 * B;
     constexpr int G = 64 / BB;
     __shared__ cx<double> s_g[G][BB * BB];
+    __shared__ cx<double> s_E[G][BB * B];     // row q: e00 row q (top) / e11 row q - B (bottom)
     __shared__ cx<double> s_A[G][B * B];
     __shared__ cx<double> s_Bm[G][B * B];
     __shared__ cx<double> s_prow[G][BB];
@@ -928,6 +936,7 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
     const bool top = q < B;
     const int i = top ? q : q - B;         // row inside the ring block
     cx<double>* Sg = s_g[gsafe];
+    cx<double>* SE = s_E[gsafe] + q * B;   // this lane's e row
     cx<double>* SA = s_A[gsafe];
     cx<double>* SB = s_Bm[gsafe];
 
@@ -943,23 +952,21 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
         const cx<double>* VH = J.VH[lead];
         const cx<double>* W = J.W[lead];
 
-        // e row (e00 on top lanes, e11 on bottom lanes), A = W, Bm = W^H
-        double er[B], ei[B];
-#pragma unroll
-        for (int j = 0; j < B; ++j) { er[j] = 0.0; ei[j] = 0.0; }
+        // e row (e00 on top lanes, e11 on bottom lanes), A = W, Bm = W^H, all in LDS
         wave_sync();
         if (act) {
-            gl_row<B>(D + (top ? 0 : B * B), i, er, ei);
+            const cx<double>* d = D + (top ? 0 : B * B) + i * B;
 #pragma unroll
             for (int j = 0; j < B; ++j) {
+                SE[j] = d[j];
                 if (top) { const cx<double> w = W[j * B + i]; SB[i * B + j] = cx<double>{w.re, -w.im}; }
                 else SA[i * B + j] = W[i * B + j];
             }
         }
         wave_sync();
 
-        // row q of z - eps, eps = [[e, V],[V^H, e']] with the e row in (er, ei)
-        // (register indices stay compile-time constants: the halves are selected by value)
+        // row q of z - eps, eps = [[e, V],[V^H, e']] (register indices stay compile-time
+        // constants: the halves are selected by value)
         auto layer_row = [&](double (&mr)[BB], double (&mi)[BB]) {
 #pragma unroll
             for (int j = 0; j < BB; ++j) { mr[j] = 0.0; mi[j] = 0.0; }
@@ -968,12 +975,28 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
                     const cx<double> c = cpl[j];
-                    const double dre = (j == i ? z.re : 0.0) - er[j];   // diagonal block entry
-                    const double dim = (j == i ? z.im : 0.0) - ei[j];
+                    const cx<double> e = SE[j];
+                    const double dre = (j == i ? z.re : 0.0) - e.re;   // diagonal block entry
+                    const double dim = (j == i ? z.im : 0.0) - e.im;
                     mr[j] = top ? dre : -c.re;
                     mi[j] = top ? dim : -c.im;
                     mr[B + j] = top ? -c.re : dre;
                     mi[B + j] = top ? -c.im : dim;
+                }
+            }
+        };
+        // out = X[row, :] * Y[:B, :B] with X (row stride B) and Y (row stride LY) in LDS
+        auto lds_mul = [&](const cx<double>* Xrow, const cx<double>* Y, int LY, double (&orr)[B], double (&oi)[B]) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) { orr[j] = 0.0; oi[j] = 0.0; }
+#pragma unroll 1
+            for (int kk = 0; kk < B; ++kk) {
+                const cx<double> x = Xrow[kk];
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const cx<double> y = Y[kk * LY + j];
+                    orr[j] = fma(x.re, y.re, fma(-x.im, y.im, orr[j]));
+                    oi[j] = fma(x.re, y.im, fma(x.im, y.re, oi[j]));
                 }
             }
         };
@@ -989,22 +1012,20 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
             }
             // top row i:    e00 += (Bm g11) A,  Bm' = (Bm g10) Bm
             // bottom row i: e11 += (A g00) Bm,  A'  = (A g01) A
-            double xr[B], xi[B], tr[B], ti[B], nr[B], ni[B];
-#pragma unroll
-            for (int j = 0; j < B; ++j) {
-                const cx<double> x = top ? SB[i * B + j] : SA[i * B + j];
-                xr[j] = x.re;
-                xi[j] = x.im;
-            }
+            const cx<double>* Xrow = (top ? SB : SA) + i * B;
             const cx<double>* g_diag = Sg + (top ? B * BB + B : 0);   // g11 (top) / g00 (bottom)
             const cx<double>* g_off = Sg + (top ? B * BB : B);        // g10 (top) / g01 (bottom)
-            row_mul_ld<B, BB>(xr, xi, g_diag, tr, ti);
+            double tr[B], ti[B], nr[B], ni[B];
+            lds_mul(Xrow, g_diag, BB, tr, ti);
             row_mul_ld<B, B>(tr, ti, top ? SA : SB, nr, ni);
             if (live) {
 #pragma unroll
-                for (int j = 0; j < B; ++j) { er[j] += nr[j]; ei[j] += ni[j]; }
+                for (int j = 0; j < B; ++j) {
+                    const cx<double> e = SE[j];
+                    SE[j] = cx<double>{e.re + nr[j], e.im + ni[j]};
+                }
             }
-            row_mul_ld<B, BB>(xr, xi, g_off, tr, ti);
+            lds_mul(Xrow, g_off, BB, tr, ti);
             row_mul_ld<B, B>(tr, ti, top ? SB : SA, nr, ni);
             wave_sync();
             if (live) {
@@ -1030,7 +1051,11 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
 
         // surface layer: eps_s = [[D0, V],[V^H, e11]]
         live = act;
-        if (act && top) gl_row<B>(D, i, er, ei);
+        if (act && top) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) SE[j] = D[i * B + j];
+        }
+        wave_sync();
         {
             double mr[BB], mi[BB];
             layer_row(mr, mi);

@@ -15,7 +15,7 @@ import numpy as np
 
 from .workload import Bias, Device, EnergyGrid, Lead, Problem
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnegf.so")
+LIB_PATH = os.environ.get("NEGF_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnegf.so")
 
 NEGF_OK, NEGF_EINVAL, NEGF_ENOMEM, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_EHIP = 0, -1, -2, -3, -4, -5
 NEGF_PENDING = 1
