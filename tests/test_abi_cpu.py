@@ -147,3 +147,42 @@ def test_binding_fails_loudly_without_library(tmp_path):
             mod.load(str(tmp_path / "nope.so"))
     finally:
         mod._lib = saved
+
+
+# ---- later entry points: argument checks that run before any HIP call ----
+def test_batch_and_graph_reject_null(lib):
+    assert lib.negf_batch_solve(None, 1, None) == NG.NEGF_EINVAL
+    assert lib.negf_batch_solve_dev(None, 1, None, None) == NG.NEGF_EINVAL
+    assert lib.negf_batch_sync(None, None) == NG.NEGF_EINVAL
+    assert lib.negf_workspace_create(None, 0) == NG.NEGF_EINVAL
+    assert lib.negf_workspace_set_grid_scale(None, 2) == NG.NEGF_EINVAL
+    assert lib.negf_workspace_set_order(None, 0) == NG.NEGF_EINVAL
+    assert lib.negf_graph_create(None, 1, None, 0, None) == NG.NEGF_EINVAL
+    assert lib.negf_graph_launch(None, None) == NG.NEGF_EINVAL
+    assert lib.negf_graph_sync(None, None) == NG.NEGF_EINVAL
+    assert lib.negf_workspace_bytes(None) == 0
+
+
+def test_server_rejects_null(lib):
+    assert lib.negf_server_create(None, 1 << 30, 4, 0) == NG.NEGF_EINVAL
+    rid = C.c_longlong()
+    assert lib.negf_server_submit(None, None, C.byref(rid)) == NG.NEGF_EINVAL
+    assert lib.negf_server_poll(None, 1, 0, None, None, None, None) == NG.NEGF_EINVAL
+    assert lib.negf_server_stats(None, None) == NG.NEGF_EINVAL
+
+
+def test_modes_and_grid_reject_bad_arguments(lib):
+    assert lib.negf_modes_create(None, 4, 3, None, None, None, None, None, 0, None) == NG.NEGF_EINVAL
+    h = C.c_void_p()
+    dev = W.random_device(4, 3, seed=2)        # not circulant: refused before any allocation
+    keep = [np.ascontiguousarray(a) for a in (dev.h_diag, dev.h_up, dev.left.h_diag, dev.left.h_up,
+                                               dev.left.tau, dev.right.h_diag, dev.right.h_up, dev.right.tau)]
+    p = [k.ctypes.data_as(C.c_void_p) for k in keep]
+    L = NG.negf_lead(dev.left.period, p[2], p[3], p[4])
+    R = NG.negf_lead(dev.right.period, p[5], p[6], p[7])
+    assert lib.negf_modes_create(C.byref(h), 4, 3, p[0], p[1], C.byref(L), C.byref(R), None, 0, None) == NG.NEGF_EINVAL
+    assert "circulant" in lib.negf_last_error().decode()
+    assert lib.negf_modes_set_potential(None, None, 0.0, 0.0) == NG.NEGF_EINVAL
+    n = C.c_int()
+    assert lib.negf_semi_adaptive_grid(None, None, 0.0, 0.0, 3.0, 1.0, None, None, None, 0, C.byref(n), None) \
+        == NG.NEGF_EINVAL
