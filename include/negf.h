@@ -239,6 +239,14 @@ typedef struct {
 } negf_schedule;
 
 negf_status negf_workspace_set_order(negf_workspace *w, int order);
+/* Basis of the lead decimation (Section 2.2.2).  1 (default): a lead whose
+ * blocks and coupling are all ring-circulant (H[i][j] depends on (j - i) mod b,
+ * as for a nanotube ring) is decimated in the ring Fourier basis, b scalar
+ * chains per node, and Sigma is transformed back; its stopping test applies
+ * decim_tol to the mode values of alpha and beta, which bound every entry, so
+ * it stops at the same step as the dense test or later.  0: every lead uses
+ * the dense b x b (or 2b x 2b) layer. */
+negf_status negf_workspace_set_lead_basis(negf_workspace *w, int ring_modes);
 /* Times every schedule setting on this job list (reps solves each, device
  * pointers, on hip_stream), keeps the fastest in w and returns it in *best. */
 negf_status negf_workspace_autotune(negf_workspace *w, int n_jobs, const negf_job *jobs, void *hip_stream,

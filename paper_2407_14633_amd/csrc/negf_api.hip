@@ -99,7 +99,34 @@ negf_status upload_lead_D(negf_device* d, int l) {
     for (int p = 0; p < ld.period; ++p)
         for (int i = 0; i < b; ++i) D[(size_t)p * b * b + (size_t)i * b + i].re += d->U_lead[l];
     HIPCHK(hipMemcpy(ld.D, D.data(), D.size() * 16, hipMemcpyHostToDevice));
+    if (ld.circ) {   // the on-site mode values (rows 0 and 1) shift with the lead potential
+        std::vector<negf_c64> m = ld.modes0;
+        for (int q = 0; q < 2 * b; ++q) m[q].re += d->U_lead[l];
+        HIPCHK(hipMemcpy(ld.modes, m.data(), m.size() * 16, hipMemcpyHostToDevice));
+    }
     return NEGF_OK;
+}
+
+bool is_circulant(const negf_c64* M, int b) {
+    for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+            const negf_c64 a = M[(size_t)i * b + j], c = M[(size_t)((j - i + b) % b)];
+            if (a.re != c.re || a.im != c.im) return false;
+        }
+    return true;
+}
+
+// eigenvalue of a circulant block on the ring Fourier vector q: sum_k C[0][k] e^{2 pi i q k / b}
+negf_c64 ring_mode(const negf_c64* C, int b, int q) {
+    double re = 0.0, im = 0.0;
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < b; ++k) {
+        const double ph = 2.0 * pi * (double)(((long long)q * k) % b) / b;
+        const double cs = std::cos(ph), sn = std::sin(ph);
+        re += C[k].re * cs - C[k].im * sn;
+        im += C[k].re * sn + C[k].im * cs;
+    }
+    return negf_c64{re, im};
 }
 
 negf_status check_lead(const negf_lead* ld, int b, const char* which) {
@@ -275,6 +302,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
             D.VH[l] = d->lead[l].VH;
             D.W[l] = d->lead[l].W;
             D.tau[l] = d->lead[l].tau;
+            D.lmodes[l] = d->lead[l].circ ? d->lead[l].modes : nullptr;
         }
         negf::RedJob& R = rj[i];
         R.Nb = d->N * d->b;
@@ -374,8 +402,13 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         // both leads in one span (sides 2), otherwise each lead in its own launch.
         {
             std::vector<negf::Span> sp[2][3];   // [period - 1][both, left only, right only]
+            std::vector<negf::Span> sp_circ;      // both leads ring-circulant: mode-basis doubling
             for (int j : g.ids) {
                 if (jobs[j].sigma_mode == 2) continue;   // cached self-energies
+                if (jd[j].lmodes[0] && jd[j].lmodes[1] && w->circ_decimation) {
+                    sp_circ.push_back({j, 0, plan[j].ne, 0, 0});
+                    continue;
+                }
                 const int p0 = jd[j].period[0], p1 = jd[j].period[1];
                 if (p0 == p1) {
                     sp[p0 - 1][0].push_back({j, 0, plan[j].ne, 0, 0});
@@ -384,6 +417,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                     sp[p1 - 1][2].push_back({j, 0, plan[j].ne, 0, 0});
                 }
             }
+            TRY(add_launch(negf::KIND_DECIMATE_CIRC, KT_DECIMATE, gi, sp_circ, 2, 0, G, false, 0));
             for (int P = 1; P <= 2; ++P) {
                 const int kind = P == 1 ? negf::KIND_DECIMATE : negf::KIND_DECIMATE2;
                 const int Gd = P == 1 ? G : 64 / (2 * B);
@@ -875,6 +909,20 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
             hipMemcpy(ld.W, W.data(), b2 * 16, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(ld.tau, src->tau, b2 * 16, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(NEGF_EHIP, "copy of lead blocks failed"));
+        // ring-circulant lead: mode values for the decimation in the ring Fourier basis
+        const int P = src->period;
+        bool circ = is_circulant(src->tau, b);
+        for (int r = 0; r < P && circ; ++r)
+            circ = is_circulant(src->h_diag + r * b2, b) && is_circulant(src->h_up + r * b2, b);
+        if (circ) {
+            ld.circ = true;
+            ld.modes0.resize((size_t)5 * b);
+            const negf_c64* blk[5] = {src->h_diag, src->h_diag + (size_t)(P - 1) * b2, src->h_up,
+                                      src->h_up + (size_t)(P - 1) * b2, src->tau};
+            for (int t = 0; t < 5; ++t)
+                for (int q = 0; q < b; ++q) ld.modes0[(size_t)t * b + q] = ring_mode(blk[t], b, q);
+            if ((s = dalloc(d, &ld.modes, (size_t)5 * b * 16)) != NEGF_OK) return bail(s);
+        }
         if ((s = upload_lead_D(d, l)) != NEGF_OK) return bail(s);
     }
     *out = d;
@@ -1026,7 +1074,7 @@ void negf_destroy(negf_device* d) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& ld : d->lead) {
-        void* lp[] = {ld.D, ld.V, ld.VH, ld.W, ld.tau};
+        void* lp[] = {ld.D, ld.V, ld.VH, ld.W, ld.tau, ld.modes};
         for (void* p : lp)
             if (p) (void)hipFree(p);
     }
@@ -1070,6 +1118,13 @@ negf_status negf_workspace_set_order(negf_workspace* w, int order) {
     if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
     if (order != 0 && order != 1) return fail(NEGF_EINVAL, "order must be 0 or 1");
     w->order = order;
+    return NEGF_OK;
+}
+
+negf_status negf_workspace_set_lead_basis(negf_workspace* w, int ring_modes) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    if (ring_modes != 0 && ring_modes != 1) return fail(NEGF_EINVAL, "ring_modes must be 0 or 1");
+    w->circ_decimation = ring_modes == 1;
     return NEGF_OK;
 }
 

@@ -43,6 +43,9 @@ struct LeadDev {
     cx<double>* VH = nullptr;       // h_up[0]^H
     cx<double>* W = nullptr;        // h_up[P-1]
     cx<double>* tau = nullptr;
+    bool circ = false;              // every lead block and tau ring-circulant
+    std::vector<negf_c64> modes0;   // [5][b] ring-mode eigenvalues, lead potential excluded
+    cx<double>* modes = nullptr;    // device copy with the lead potential added
 };
 
 // A growable device buffer (contents are not preserved when it grows).
@@ -80,6 +83,7 @@ struct negf_workspace {
     // schedule knobs (results do not depend on them)
     int grid_scale = 1;       // persistent workgroups per (resident workgroups x CU)
     int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
+    bool circ_decimation = true;   // ring-circulant leads decimated in the ring Fourier basis
     bool capturing = false;   // enqueue is being recorded into a graph
 };
 

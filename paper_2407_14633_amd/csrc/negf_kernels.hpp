@@ -243,6 +243,9 @@ struct JobDesc {
     const cx<double>* VH[2];  // h_up[0]^H
     const cx<double>* W[2];   // h_up[period-1]
     const cx<double>* tau[2]; // H_{device edge, lead ring 0}
+    // ring-circulant leads: per lead [5][b] eigenvalues of D_0, D_{P-1}, h_up[0],
+    // h_up[P-1], tau on the ring Fourier vectors (lead potential included); null otherwise
+    const cx<double>* lmodes[2];
 };
 
 // A span: the nodes [e0, e0+cnt) of one job that one kernel launch covers
@@ -1066,6 +1069,129 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
         if (act && q == 0) {
             J.iters[(size_t)k * 2 + lead] = it_done;
             if (!converged) atomicOr(&J.status[k], 1);
+        }
+        wave_sync();
+    }
+}
+
+// ---- Ring-circulant leads: every lead block C satisfies C[i][j] = C[0][(j - i) mod b],
+// so the ring Fourier vectors diagonalise all of them at once and the doubling runs
+// on b independent scalar chains (lane = mode q): the same Sancho-Rubio steps with
+// 1 x 1 blocks (period 1) or with the 2 x 2 layer [[z - e00, -v],[-v*, z - e11]]
+// inverted in closed form (period 2, no single-ring Schur complement).  A chain is
+// done when |A_q|, |Bm_q| < tol for every mode (a circulant block's entries are
+// averages of its eigenvalues, so this is at least as strict as the entrywise rule).
+// Sigma_q = tau_q g_q conj(tau_q); back in the ring basis Sigma[i][j] =
+// c_{(i-j) mod b}, c_d = (1/b) sum_q Sigma_q e^{2 pi i q d / b}.
+__device__ __forceinline__ cx<double> cmul(cx<double> a, cx<double> b) {
+    return cx<double>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+    double rr, ri;
+    crecip<double>(b.re, b.im, rr, ri);
+    return cmul(a, cx<double>{rr, ri});
+}
+
+template <int B>
+__global__ __launch_bounds__(64) void k_decimate_circ(Sched S) {
+    constexpr int G = 64 / B;
+    __shared__ cx<double> s_sig[G][B];
+    __shared__ cx<double> s_tw[B];           // e^{2 pi i k / B}
+    __shared__ int s_live[G];
+    const int lane = threadIdx.x;
+    const int gi = lane / B;
+    const int gsafe = gi < G ? gi : 0;
+    const int q = lane - gi * B;             // mode
+    if (lane < B) {
+        double sn, cs;
+        sincospi(2.0 * lane / B, &sn, &cs);
+        s_tw[lane] = cx<double>{cs, sn};
+    }
+    wave_sync();
+    Unit u;
+    while (next_unit<G>(S, u)) {
+        const JobDesc& J = S.jobs[u.job];
+        const int lead = u.side;
+        const bool act = (gi < G) && (gi < u.cnt);
+        const int k = u.e0 + (act ? gi : 0);
+        const cx<double> z = J.z[k];
+        const cx<double>* m = J.lmodes[lead];
+        const bool two = J.period[lead] == 2;
+        const cx<double> e0 = m[0 * B + q], e1 = m[1 * B + q], v = m[2 * B + q], w = m[3 * B + q];
+        const cx<double> tq = m[4 * B + q];
+        const cx<double> vc{v.re, -v.im}, wc{w.re, -w.im};
+        // state: period 1: e (e00), es (e11 slot); period 2: e00, e11 (== eps_s(1,1))
+        cx<double> E0 = e0, E1 = two ? e1 : e0, A = w, Bm = wc;
+        bool live = act;
+        int it_done = S.maxit;
+        for (int it = 1; it <= S.maxit; ++it) {
+            if (live) {
+                if (two) {
+                    const cx<double> a{z.re - E0.re, z.im - E0.im}, c{z.re - E1.re, z.im - E1.im};
+                    const cx<double> ac = cmul(a, c), vv{v.re * v.re + v.im * v.im, 0.0};
+                    const cx<double> det{ac.re - vv.re, ac.im};
+                    const cx<double> g00 = cdiv(c, det), g11 = cdiv(a, det);
+                    const cx<double> g01 = cdiv(v, det), g10 = cdiv(vc, det);
+                    const cx<double> dE1 = cmul(cmul(A, g00), Bm), dE0 = cmul(cmul(Bm, g11), A);
+                    const cx<double> nA = cmul(cmul(A, g01), A), nB = cmul(cmul(Bm, g10), Bm);
+                    E1 = cx<double>{E1.re + dE1.re, E1.im + dE1.im};
+                    E0 = cx<double>{E0.re + dE0.re, E0.im + dE0.im};
+                    A = nA;
+                    Bm = nB;
+                } else {
+                    const cx<double> g = cdiv(cx<double>{1.0, 0.0}, cx<double>{z.re - E0.re, z.im - E0.im});
+                    const cx<double> agb = cmul(cmul(A, g), Bm), bga = cmul(cmul(Bm, g), A);
+                    E1 = cx<double>{E1.re + agb.re, E1.im + agb.im};                       // eps_s
+                    E0 = cx<double>{E0.re + agb.re + bga.re, E0.im + agb.im + bga.im};    // eps
+                    const cx<double> nA = cmul(cmul(A, g), A), nB = cmul(cmul(Bm, g), Bm);
+                    A = nA;
+                    Bm = nB;
+                }
+            }
+            // a chain stops when all its modes are below tol
+            if (q == 0 && gi < G) s_live[gi] = 0;
+            wave_sync();
+            if (live && !(hypot(A.re, A.im) < S.tol && hypot(Bm.re, Bm.im) < S.tol)) s_live[gsafe] = 1;
+            wave_sync();
+            if (live && s_live[gsafe] == 0) { live = false; it_done = it; }
+            wave_sync();
+            if (__all(!live)) break;
+        }
+        const bool converged = act && !live;
+        // surface Green's function of the mode and its self-energy
+        cx<double> gs;
+        if (two) {
+            const cx<double> a{z.re - e0.re, z.im - e0.im}, c{z.re - E1.re, z.im - E1.im};
+            const cx<double> ac = cmul(a, c);
+            gs = cdiv(c, cx<double>{ac.re - (v.re * v.re + v.im * v.im), ac.im});
+        } else {
+            gs = cdiv(cx<double>{1.0, 0.0}, cx<double>{z.re - E1.re, z.im - E1.im});
+        }
+        const double t2 = tq.re * tq.re + tq.im * tq.im;
+        if (act) s_sig[gsafe][q] = cx<double>{t2 * gs.re, t2 * gs.im};
+        wave_sync();
+        if (act) {
+            // c_d for d = q, then row q of Sigma: Sigma[q][j] = c_{(q - j) mod B}
+            cx<double> cd{0.0, 0.0};
+            for (int p = 0; p < B; ++p) {
+                const cx<double> sp = s_sig[gsafe][p], tw = s_tw[(p * q) % B];
+                cd.re += sp.re * tw.re - sp.im * tw.im;
+                cd.im += sp.re * tw.im + sp.im * tw.re;
+            }
+            cd.re *= 1.0 / B;
+            cd.im *= 1.0 / B;
+            wave_sync();
+            s_sig[gsafe][q] = cd;       // every lane has read s_sig before this write
+            wave_sync();
+            cx<double>* out = J.sigma + ((size_t)k * 2 + lead) * B * B + (size_t)q * B;
+            for (int j = 0; j < B; ++j) out[j] = s_sig[gsafe][(q - j + B) % B];
+            if (q == 0) {
+                J.iters[(size_t)k * 2 + lead] = it_done;
+                if (!converged) atomicOr(&J.status[k], 1);
+            }
+        } else {
+            wave_sync();
+            wave_sync();
         }
         wave_sync();
     }

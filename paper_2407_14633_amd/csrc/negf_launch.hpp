@@ -6,7 +6,7 @@
 
 namespace negf {
 
-enum { KIND_DECIMATE = 0, KIND_DECIMATE2, KIND_RECUR64, KIND_RECUR32, KIND_CDIAG64, KIND_CDIAG32, KIND_COLUMN64, KIND_COLUMN32,
+enum { KIND_DECIMATE = 0, KIND_DECIMATE2, KIND_DECIMATE_CIRC, KIND_RECUR64, KIND_RECUR32, KIND_CDIAG64, KIND_CDIAG32, KIND_COLUMN64, KIND_COLUMN32,
        KIND_COUNT };
 
 struct Launchers {
@@ -25,6 +25,9 @@ struct LaunchImpl {
     static void decimate2(const Sched& a, int grid, size_t, hipStream_t s) {
         hipLaunchKernelGGL(k_decimate2<B>, dim3(grid), dim3(64), 0, s, a);
     }
+    static void decimate_circ(const Sched& a, int grid, size_t, hipStream_t s) {
+        hipLaunchKernelGGL(k_decimate_circ<B>, dim3(grid), dim3(64), 0, s, a);
+    }
     template <typename T>
     static void recur(const Sched& a, int grid, size_t dyn, hipStream_t s) {
         hipLaunchKernelGGL((k_recur<T, B>), dim3(grid), dim3(64), dyn, s, a);
@@ -40,10 +43,10 @@ struct LaunchImpl {
     static const Launchers* table() {
         static const Launchers t = {
             B, 64 / B,
-            {&decimate, &decimate2, &recur<double>, &recur<float>, &cdiag<double>, &cdiag<float>, &column<double>,
+            {&decimate, &decimate2, &decimate_circ, &recur<double>, &recur<float>, &cdiag<double>, &cdiag<float>, &column<double>,
              &column<float>},
             {reinterpret_cast<const void*>(&k_decimate<B>), reinterpret_cast<const void*>(&k_decimate2<B>),
-             reinterpret_cast<const void*>(&k_recur<double, B>),
+             reinterpret_cast<const void*>(&k_decimate_circ<B>), reinterpret_cast<const void*>(&k_recur<double, B>),
              reinterpret_cast<const void*>(&k_recur<float, B>), reinterpret_cast<const void*>(&k_cdiag<double, B>),
              reinterpret_cast<const void*>(&k_cdiag<float, B>), reinterpret_cast<const void*>(&k_column<double, B>),
              reinterpret_cast<const void*>(&k_column<float, B>)}};

@@ -29,7 +29,7 @@ EXPORTED = [
     "negf_set_profiling", "negf_kernel_times", "negf_device_bytes", "negf_destroy", "negf_last_error",
     "negf_workspace_create", "negf_workspace_destroy", "negf_workspace_bytes", "negf_workspace_set_profiling",
     "negf_workspace_kernel_times", "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev",
-    "negf_batch_sync", "negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create",
+    "negf_batch_sync", "negf_workspace_set_order", "negf_workspace_set_lead_basis", "negf_workspace_autotune", "negf_graph_create",
     "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy", "negf_server_create", "negf_server_submit",
     "negf_server_poll", "negf_server_stats", "negf_server_destroy", "negf_modes_create",
     "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy", "negf_semi_adaptive_grid",
@@ -140,6 +140,7 @@ def load(path: str = LIB_PATH):
     lib.negf_batch_solve_dev.argtypes = [vp, i, C.POINTER(negf_job), vp]
     lib.negf_batch_sync.argtypes = [vp, C.POINTER(i)]
     lib.negf_workspace_set_order.argtypes = [vp, i]
+    lib.negf_workspace_set_lead_basis.argtypes = [vp, i]
     lib.negf_workspace_autotune.argtypes = [vp, i, C.POINTER(negf_job), vp, i, C.POINTER(negf_schedule)]
     lib.negf_graph_create.argtypes = [C.POINTER(vp), i, C.POINTER(negf_job), sz, vp]
     lib.negf_graph_launch.argtypes = [vp, vp]
@@ -164,8 +165,8 @@ def load(path: str = LIB_PATH):
     lib.negf_server_destroy.restype = None
     for name in ("negf_server_create", "negf_server_submit", "negf_server_poll", "negf_server_stats"):
         getattr(lib, name).restype = C.c_int
-    for name in ("negf_workspace_set_order", "negf_workspace_autotune", "negf_graph_create", "negf_graph_launch",
-                 "negf_graph_sync"):
+    for name in ("negf_workspace_set_order", "negf_workspace_set_lead_basis", "negf_workspace_autotune",
+                 "negf_graph_create", "negf_graph_launch", "negf_graph_sync"):
         getattr(lib, name).restype = C.c_int
     for name in ("negf_workspace_create", "negf_workspace_set_profiling", "negf_workspace_kernel_times",
                  "negf_workspace_set_grid_scale", "negf_batch_solve", "negf_batch_solve_dev", "negf_batch_sync"):
@@ -411,6 +412,10 @@ class Workspace:
 
     def set_order(self, order: int):
         _check(load().negf_workspace_set_order(self.h, int(order)))
+
+    def set_lead_basis(self, ring_modes: int):
+        """1: ring-circulant leads decimated in the ring Fourier basis; 0: dense layers."""
+        _check(load().negf_workspace_set_lead_basis(self.h, int(ring_modes)))
 
     def autotune(self, jobs, stream=None, reps: int = 2) -> negf_schedule:
         """Times every schedule on these device jobs and keeps the fastest."""

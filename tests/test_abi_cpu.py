@@ -157,6 +157,7 @@ def test_batch_and_graph_reject_null(lib):
     assert lib.negf_workspace_create(None, 0) == NG.NEGF_EINVAL
     assert lib.negf_workspace_set_grid_scale(None, 2) == NG.NEGF_EINVAL
     assert lib.negf_workspace_set_order(None, 0) == NG.NEGF_EINVAL
+    assert lib.negf_workspace_set_lead_basis(None, 1) == NG.NEGF_EINVAL
     assert lib.negf_graph_create(None, 1, None, 0, None) == NG.NEGF_EINVAL
     assert lib.negf_graph_launch(None, None) == NG.NEGF_EINVAL
     assert lib.negf_graph_sync(None, None) == NG.NEGF_EINVAL

@@ -95,6 +95,35 @@ def test_batch_matches_oracle(gpu_lib):
         d.close()
 
 
+def test_ring_mode_decimation_matches_dense(gpu_lib):
+    """Nanotube leads are ring-circulant: the decimation in the ring Fourier basis
+    and the dense 2b x 2b layer give the same solve to the FP64 gate."""
+    negf = gpu_lib
+    ps = small_batch(seed=17, n_dev=5)
+    rnd = W.random_device(5, 6, seed=21, period=2, scale=0.6)
+    rb = W.Bias(0.1, -0.1, 0.05, 0.04)
+    ps.append(W.Problem("rand", rnd, np.zeros(30), 0.0, 0.0, rb,
+                        W.nonequilibrium_grid(W.gershgorin_lower(rnd, np.zeros(30)) - 1.0, rb, 5, 6), eta=1e-4))
+    devs = open_devices(negf, ps)
+    jobs = [negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)]
+    with negf.Workspace() as ws:
+        modes = ws.solve(jobs)
+        ws.set_lead_basis(0)
+        dense = ws.solve(jobs)
+        ws.set_lead_basis(1)
+        again = ws.solve(jobs)
+    assert_same(again, modes, "ring-mode basis after a dense solve")
+    # the non-circulant device takes the dense kernel either way
+    assert_same(modes[-1:], dense[-1:], "random leads")
+    for k, (m, d) in enumerate(zip(modes, dense)):
+        eq, eT = rel(m.charge, d.charge), rel(m.T, d.T)
+        eI = abs(m.current - d.current) / max(abs(d.current), 1e-300)
+        say("modes vs dense", k, ps[k].device.b, f"{eq:.2e} {eT:.2e} {eI:.2e}")
+        assert eq < 1e-10 and eT < 1e-9 and eI < 1e-9
+    for d in devs:
+        d.close()
+
+
 def test_batch_chunking_and_grid_scale_invariant(gpu_lib):
     negf = gpu_lib
     ps = small_batch(seed=13, n_dev=6)
