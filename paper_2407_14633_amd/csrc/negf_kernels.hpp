@@ -38,7 +38,9 @@
 
 namespace negf {
 
-template <typename T> struct cx { T re, im; };
+// aligned to its full size so that one element moves with one 128-bit (FP64)
+// or 64-bit (FP32) LDS or global access
+template <typename T> struct alignas(2 * sizeof(T)) cx { T re, im; };
 
 // ------------------------------------------------------------ scalar helpers
 template <typename T>
@@ -59,6 +61,29 @@ template <typename T>
 __device__ __forceinline__ cx<T> ld_cx(const cx<double>* p) {
     const cx<double> v = *p;
     return cx<T>{T(v.re), T(v.im)};
+}
+
+// Loads and stores through the global address space: global (not flat)
+// instructions, which count only against the vector-memory counter, so waits on
+// LDS results never also wait for HBM traffic.
+template <typename T>
+__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
+    const __attribute__((address_space(1))) cx<T>* g = (const __attribute__((address_space(1))) cx<T>*)(p);
+    return cx<T>{g->re, g->im};
+}
+template <typename T>
+__device__ __forceinline__ T gload_s(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(cx<T>* p, cx<T> v) {
+    __attribute__((address_space(1))) cx<T>* g = (__attribute__((address_space(1))) cx<T>*)(p);
+    g->re = v.re;
+    g->im = v.im;
+}
+template <typename T>
+__device__ __forceinline__ void gstore_s(T* p, T v) {
+    *(__attribute__((address_space(1))) T*)(p) = v;
 }
 
 // Per-group slice of LDS used by the block toolkit.
@@ -88,12 +113,42 @@ __device__ __forceinline__ int key_row(unsigned key, int B) {
 }
 
 // --------------------------------------------------------------- inversion
+// Pins a value in registers at this point of the instruction stream: the
+// compiler cannot compute it later or keep an earlier copy alive past it, and
+// memory accesses are not moved across.
+template <typename T>
+__device__ __forceinline__ void pin(T& v) { asm volatile("" : "+v"(v) : : "memory"); }
+
+// Column of update slot t at pivot step k: all columns but k, and but k+1 while
+// k+1 < B (updated ahead for the look-ahead); B when the slot is unused.
+template <int B>
+__device__ __forceinline__ constexpr int gj_col(int t, int k) {
+    return k + 1 < B ? (t < k ? t : t + 2) : t;
+}
+
+// Pivot-row entries in flight per chunk of the elimination update.
+#ifndef GJ_CHUNK
+#define GJ_CHUNK 8
+#endif
+
+// 1 / (re + i im) = conj / |.|^2, the form every pivot reciprocal uses.
+template <typename T>
+__device__ __forceinline__ void pivot_recip(T re, T im, T& qr, T& qi) {
+    const T inv_d = T(1) / (re * re + im * im);
+    qr = re * inv_d;
+    qi = -im * inv_d;
+}
+
 // In-place Gauss-Jordan inversion with partial pivoting of the B x B matrix
 // whose row r sits in (ar, ai) of lane r.
 //  * Pivot of column k: the unused row of largest |re|+|im|, by an LDS max over
 //    keys packing the magnitude (float, top 25 bits) with the row (low 7 bits).
-//    The key of column k+1 is published while column k's update is still
-//    running (look-ahead), so the search costs no extra round trip.
+//    Column k+1 is updated first and its key published while column k's update
+//    is still running (look-ahead); the key is read back right away, so the
+//    next pivot is known before the bulk of the update is done.
+//  * Every row also computes the reciprocal of its column k+1 entry during step
+//    k; the row that becomes pivot publishes it in place of its pivot entry, so
+//    the division is off the chain of dependent steps.
 //  * Rows are never exchanged: the pivot row is relabelled, and the final
 //    scatter writes the un-permuted inverse to g.stage.
 //  * Row scaling is deferred: a pivot row keeps its unscaled values R_p, with
@@ -108,44 +163,88 @@ __device__ __forceinline__ void gj_inverse(T (&ar)[B], T (&ai)[B], const Grp<T, 
     bool used = !g.act;
     int my_k = 0;
     T sr = T(1), si = T(0);   // deferred row scale
+    T cr, ci;                 // 1 / (this row's entry in the next pivot column)
+    pivot_recip(ar[0], ai[0], cr, ci);
+    asm volatile("" : "+v"(cr), "+v"(ci));   // computed here, not inside the pivot branch
     if (!used) atomicMax(&g.keys[0], pivot_key(ar[0], ai[0], g.r));
     wave_sync();
+    int p = key_row(g.keys[0], B);
     // fully unrolled for every block size used (up to 48 rows): the register rows may
     // only be indexed by compile-time constants
 #pragma clang loop unroll(full)
     for (int k = 0; k < B; ++k) {
-        const int p = key_row(g.keys[k], B);
         const bool piv = g.act && (g.r == p);
         if (piv) {
 #pragma unroll
-            for (int j = 0; j < B; ++j) g.prow[j] = cx<T>{ar[j], ai[j]};
+            for (int j = 0; j < B; ++j) g.prow[j] = j == k ? cx<T>{cr, ci} : cx<T>{ar[j], ai[j]};
         }
         wave_sync();
-        const cx<T> pk = g.prow[k];
-        const T inv_d = T(1) / (pk.re * pk.re + pk.im * pk.im);
-        const T qr = pk.re * inv_d, qi = -pk.im * inv_d;          // 1/P_k
+        const cx<T> q = g.prow[k];                                 // 1 / P_k
+        const cx<T> q1 = g.prow[k + 1 < B ? k + 1 : k];
         // f = R_ik / P_k for the other rows, 0 for the pivot row
-        T fr = ar[k] * qr - ai[k] * qi;
-        T fi = ar[k] * qi + ai[k] * qr;
+        T fr = ar[k] * q.re - ai[k] * q.im;
+        T fi = ar[k] * q.im + ai[k] * q.re;
         fr = piv ? T(0) : fr;
         fi = piv ? T(0) : fi;
+        // pivot bookkeeping without a branch (a branch would wait for q alone)
+        sr = piv ? q.re : sr;
+        si = piv ? q.im : si;
+        used = used || piv;
+        my_k = piv ? k : my_k;
+        unsigned key_next = 0u;
         if (k + 1 < B) {
-            const cx<T> q = g.prow[k + 1];
-            ar[k + 1] = fma(-fr, q.re, fma(fi, q.im, ar[k + 1]));
-            ai[k + 1] = fma(-fr, q.im, fma(-fi, q.re, ai[k + 1]));
-            if (!used && !piv) atomicMax(&g.keys[k + 1], pivot_key(ar[k + 1], ai[k + 1], g.r));
+            ar[k + 1] = fma(-fr, q1.re, fma(fi, q1.im, ar[k + 1]));
+            ai[k + 1] = fma(-fr, q1.im, fma(-fi, q1.re, ai[k + 1]));
+            if (!used) atomicMax(&g.keys[k + 1], pivot_key(ar[k + 1], ai[k + 1], g.r));
+            wave_sync();
+            key_next = g.keys[k + 1];
+            pivot_recip(ar[k + 1], ai[k + 1], cr, ci);
+            asm volatile("" : "+v"(cr), "+v"(ci));
         }
+        // The remaining columns, their pivot-row entries read GJ_CHUNK at a time one
+        // chunk ahead of the arithmetic; the next key is read before them and
+        // decoded only after the first chunk is out, so LDS latency overlaps FMAs.
+        // slot t < B - 1 stands for column gj_col(t, k): every column but k (and but
+        // k+1 while k+1 < B, whose update was done above); gj_col = B marks no column
+        constexpr int NJ = B - 1 > 0 ? B - 1 : 0;
+        constexpr int CW = B >= 20 ? GJ_CHUNK / 2 : GJ_CHUNK;   // fewer in flight for wide rows
+        constexpr int C = CW < NJ ? CW : (NJ > 0 ? NJ : 1);
+        constexpr int NC = NJ > 0 ? (NJ + C - 1) / C : 0;
+        cx<T> qv[2][C];
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
-            if (j == k || j == k + 1) continue;
-            const cx<T> q = g.prow[j];
-            ar[j] = fma(-fr, q.re, fma(fi, q.im, ar[j]));
-            ai[j] = fma(-fr, q.im, fma(-fi, q.re, ai[j]));
+        for (int q = 0; q < C; ++q)
+            if (q < NJ && gj_col<B>(q, k) < B) qv[0][q] = g.prow[gj_col<B>(q, k)];
+        asm volatile("" : "+v"(key_next) : : "memory");   // decoded only after the reads are out
+        const int p_next = k + 1 < B ? key_row(key_next, B) : p;
+#pragma clang loop unroll(full)
+        for (int c = 0; c < NC; ++c) {
+            if (c + 1 < NC) {
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    const int t = (c + 1) * C + q;
+                    if (t < NJ && gj_col<B>(t, k) < B) qv[(c + 1) & 1][q] = g.prow[gj_col<B>(t, k)];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if (c * C + q < NJ && gj_col<B>(c * C + q, k) < B) { pin(qv[c & 1][q].re); pin(qv[c & 1][q].im); }
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const int t = c * C + q;
+                if (t < NJ && gj_col<B>(t, k) < B) {
+                    const int j = gj_col<B>(t, k);
+                    const cx<T> qj = qv[c & 1][q];
+                    ar[j] = fma(-fr, qj.re, fma(fi, qj.im, ar[j]));
+                    ai[j] = fma(-fr, qj.im, fma(-fi, qj.re, ai[j]));
+                    pin(ar[j]);
+                    pin(ai[j]);
+                }
+            }
         }
         ar[k] = piv ? T(1) : -fr;
         ai[k] = piv ? T(0) : -fi;
-        if (piv) { sr = qr; si = qi; used = true; my_k = k; }
         wave_sync();
+        p = p_next;
     }
     // apply the deferred scale, then scatter: lane with logical row my_k holds
     // column perm[j] in register j
@@ -181,6 +280,89 @@ __device__ __forceinline__ void row_mul(const T (&xr)[B], const T (&xi)[B], cons
             oi[j] = fma(a, q.im, fma(b, q.re, oi[j]));
         }
     }
+}
+
+// out = x * Y like row_mul, with the LDS reads of Y issued C elements at a time
+// one chunk ahead of the arithmetic on the previous chunk, so their latency
+// hides behind the FMAs.  Same order of operations as row_mul.
+template <typename T, int B, int C = (B >= 20 ? 4 : 8)>
+__device__ __forceinline__ void row_mul_pipe(const T (&xr)[B], const T (&xi)[B], const cx<T>* Y,
+                                             T (&orr)[B], T (&oi)[B]) {
+    constexpr int NE = B * B, NC = (NE + C - 1) / C;
+#pragma unroll
+    for (int j = 0; j < B; ++j) { orr[j] = T(0); oi[j] = T(0); }
+    cx<T> buf[2][C];
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+        if (q < NE) buf[0][q] = Y[q];
+#pragma clang loop unroll(full)
+    for (int c = 0; c < NC; ++c) {
+        if (c + 1 < NC) {
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if ((c + 1) * C + q < NE) buf[(c + 1) & 1][q] = Y[(c + 1) * C + q];
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+            if (c * C + q < NE) { pin(buf[c & 1][q].re); pin(buf[c & 1][q].im); }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int e = c * C + q;
+            if (e < NE) {
+                const int k = e / B, j = e % B;
+                const cx<T> y = buf[c & 1][q];
+                orr[j] = fma(xr[k], y.re, fma(-xi[k], y.im, orr[j]));
+                oi[j] = fma(xr[k], y.im, fma(xi[k], y.re, oi[j]));
+                pin(orr[j]);
+                pin(oi[j]);
+            }
+        }
+    }
+}
+
+// Re sum_j (x Y)[j] conj(x[j]) without keeping the row x Y: element (k, j) of Y is
+// taken column by column (j outer, k inner), read C elements ahead as in
+// row_mul_pipe.  Same order of operations as row_mul followed by the dot product.
+template <typename T, int B, int C = (B >= 20 ? 4 : 8)>
+__device__ __forceinline__ T row_quad_pipe(const T (&xr)[B], const T (&xi)[B], const cx<T>* Y) {
+    constexpr int NE = B * B, NC = (NE + C - 1) / C;
+    T acc = T(0), vr = T(0), vi = T(0);
+    cx<T> buf[2][C];
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+        if (q < NE) buf[0][q] = Y[(q % B) * B + q / B];
+#pragma clang loop unroll(full)
+    for (int c = 0; c < NC; ++c) {
+        if (c + 1 < NC) {
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const int e = (c + 1) * C + q;
+                if (e < NE) buf[(c + 1) & 1][q] = Y[(e % B) * B + e / B];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+            if (c * C + q < NE) { pin(buf[c & 1][q].re); pin(buf[c & 1][q].im); }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int e = c * C + q;
+            if (e < NE) {
+                const int j = e / B, k = e % B;
+                const cx<T> y = buf[c & 1][q];
+                vr = fma(xr[k], y.re, fma(-xi[k], y.im, vr));
+                vi = fma(xr[k], y.im, fma(xi[k], y.re, vi));
+                if (k == B - 1) {
+                    acc = fma(vr, xr[j], fma(vi, xi[j], acc));
+                    vr = T(0);
+                    vi = T(0);
+                }
+            }
+        }
+        pin(vr);
+        pin(vi);
+        pin(acc);
+    }
+    return acc;
 }
 
 // out = X[r,:] * Y with both operands in LDS; the k loop is not unrolled so the
@@ -316,8 +498,12 @@ __device__ __forceinline__ bool next_unit(const Sched& S, Unit& u, bool items = 
 template <typename T, int B>
 __device__ __forceinline__ void stage_to_global(const cx<T>* S, cx<T>* dst, int r, bool act) {
     if (act) {
+        // the addresses are formed here, not hoisted ahead where they would hold
+        // registers through the inversion
+        cx<T>* d = dst + r;
+        asm volatile("" : "+v"(d));
 #pragma unroll
-        for (int t = 0; t < B; ++t) dst[t * B + r] = S[t * B + r];
+        for (int t = 0; t < B; ++t) d[t * B] = S[t * B + r];
     }
 }
 
@@ -382,7 +568,7 @@ __device__ __forceinline__ void invert_fp64_into(const JobDesc& J, int e, int n,
 }
 
 template <typename T, int B>
-__global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_recur(Sched S) {
+__global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per_eu(NEGF_RGF_WAVES, NEGF_RGF_WAVES))) void k_recur(Sched S) {
     constexpr int G = 64 / B;
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr int G64 = kF32 ? G : 1;   // FP64 boundary buffers (FP32-bulk form only)
@@ -391,7 +577,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_recur(Sched S) {
     __shared__ unsigned s_keys[G][B];
     __shared__ cx<double> s_stage64[G64][kF32 ? B * B : 1];
     __shared__ cx<double> s_prow64[G64][kF32 ? B : 1];
-    extern __shared__ unsigned char s_dyn[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
@@ -513,7 +699,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_recur(Sched S) {
 // ================================================================ k_cdiag ==
 // Item = (contour node, ring n): G_nn = (a_n - x_n - y_n)^{-1}, diagonal kept.
 template <typename T, int B>
-__global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_cdiag(Sched S) {
+__global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per_eu(NEGF_RGF_WAVES, NEGF_RGF_WAVES))) void k_cdiag(Sched S) {
     constexpr int G = 64 / B;
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr int G64 = kF32 ? G : 1;
@@ -605,7 +791,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_cdiag(Sched S) {
 // Each ring's diag(W Gamma W^H) is written; the right chain ends with
 // T_LR = Tr[Gamma_L W_0 Gamma_R W_0^H] (Eq. 5).
 template <typename T, int B>
-__global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
+__global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per_eu(NEGF_RGF_WAVES, NEGF_RGF_WAVES))) void k_column(Sched S) {
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_gam[G][B * B];
@@ -630,7 +816,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
             const cx<double>* s = J.sigma + ((size_t)e * 2 + lead) * B * B;
 #pragma unroll
             for (int j = 0; j < B; ++j) {
-                const cx<double> a = s[r * B + j], b = s[j * B + r];
+                const cx<double> a = gload(s + r * B + j), b = gload(s + j * B + r);
                 // Gamma[r][j] = i (Sigma[r][j] - conj(Sigma[j][r]))
                 Gm[r * B + j] = cx<T>{T(-(a.im + b.im)), T(a.re - b.re)};
             }
@@ -643,13 +829,12 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
         if (act) {
             const cx<T>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
 #pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<T> v = w0[j]; wr[j] = v.re; wi[j] = v.im; }
+            for (int j = 0; j < B; ++j) { const cx<T> v = gload(w0 + j); wr[j] = v.re; wi[j] = v.im; }
         }
         stage_row<T, B>(wr, wi, St, r, act);
         wave_sync();
         T* aout = reinterpret_cast<T*>(J.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
 
-        T vr[B], vi[B];
         for (int s = 0; s < N; ++s) {
             const int n = lead ? N - 1 - s : s;
             // propagator row for this step, loaded ahead of the Gamma product
@@ -659,26 +844,27 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
             if (act && s < N - 1) {
                 const cx<T>* p = store + ((size_t)n * B + r) * B;
 #pragma unroll
-                for (int j = 0; j < B; ++j) { const cx<T> v = p[j]; pr[j] = -v.re; pi[j] = -v.im; }
+                for (int j = 0; j < B; ++j) { const cx<T> v = gload(p + j); pr[j] = -v.re; pi[j] = -v.im; }
             }
-            // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j])
-            row_mul<T, B>(wr, wi, Gm, vr, vi);
-            if (act) {
-                T acc = T(0);
-#pragma unroll
-                for (int j = 0; j < B; ++j) acc = fma(vr[j], wr[j], fma(vi[j], wi[j], acc));
-                aout[(size_t)n * B + r] = acc;
-            }
+            // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j]).  Gamma does not
+            // change along the chain; its offset is made opaque each step so that its
+            // B*B reads are not hoisted out of the loop into (spilled) registers.
+            int goff = gsafe * B * B;
+            asm volatile("" : "+v"(goff));
+            const T acc = row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
+            if (act) gstore_s(aout + (size_t)n * B + r, acc);
             if (s == N - 1) break;
             // W_next[r][:] = -sum_k P[r][k] W[k][:],  P = y~_n (right) or x~_n (left)
-            row_mul<T, B>(pr, pi, St, wr, wi);
+            row_mul_pipe<T, B>(pr, pi, St, wr, wi);
             wave_sync();
             stage_row<T, B>(wr, wi, St, r, act);
             wave_sync();
         }
         if (lead == 1) {
-            // W = G_{0,N-1} (in St and registers), v = W Gamma_R (registers).
+            // W = G_{0,N-1} (in St and registers), v = W Gamma_R.
             // T_LR = sum_{r,j'} Gamma_L[j'][r] (W Gamma_R W^H)[r][j']
+            T vr[B], vi[B];
+            row_mul<T, B>(wr, wi, Gm, vr, vi);
             double t = 0.0;
             if (act) {
                 const cx<double>* sl = J.sigma + ((size_t)e * 2 + 0) * B * B;
@@ -690,7 +876,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
                         mr += (double)vr[j] * (double)wv.re + (double)vi[j] * (double)wv.im;
                         mi += (double)vi[j] * (double)wv.re - (double)vr[j] * (double)wv.im;
                     }
-                    const cx<double> a = sl[jp * B + r], b = sl[r * B + jp];
+                    const cx<double> a = gload(sl + jp * B + r), b = gload(sl + r * B + jp);
                     const double gre = -(a.im + b.im), gim = a.re - b.re;   // Gamma_L[jp][r]
                     t += gre * mr - gim * mi;
                 }
@@ -703,7 +889,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) void k_column(Sched S) {
             if (act && r == 0) {
                 double sum = 0.0;
                 for (int q = 0; q < B; ++q) sum += red[q];
-                J.Tout[ir] = sum;
+                gstore_s(J.Tout + ir, sum);
             }
         }
         wave_sync();
