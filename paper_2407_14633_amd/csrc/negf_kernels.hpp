@@ -503,7 +503,7 @@ __device__ __forceinline__ void stage_to_global(const cx<T>* S, cx<T>* dst, int 
         cx<T>* d = dst + r;
         asm volatile("" : "+v"(d));
 #pragma unroll
-        for (int t = 0; t < B; ++t) d[t * B] = S[t * B + r];
+        for (int t = 0; t < B; ++t) gstore(d + t * B, S[t * B + r]);
     }
 }
 
@@ -514,7 +514,7 @@ __device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r,
     if (!J.hdiag_zero) {
         const cx<double>* h = J.hdiag + ((size_t)n * B + r) * B;
 #pragma unroll
-        for (int j = 0; j < B; ++j) { xr[j] -= T(h[j].re); xi[j] -= T(h[j].im); }
+        for (int j = 0; j < B; ++j) { const cx<double> hv = gload(h + j); xr[j] -= T(hv.re); xi[j] -= T(hv.im); }
     }
     const T dre = T(z.re - u), dim = T(z.im);   // diagonal formed in FP64, then rounded
 #pragma unroll
@@ -527,7 +527,7 @@ __device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r,
             if ((lr == 0 && n == 0) || (lr == 1 && n == J.N - 1)) {
                 const cx<double>* sg = J.sigma + ((size_t)e * 2 + lr) * B * B + (size_t)r * B;
 #pragma unroll
-                for (int j = 0; j < B; ++j) { xr[j] -= T(sg[j].re); xi[j] -= T(sg[j].im); }
+                for (int j = 0; j < B; ++j) { const cx<double> sv = gload(sg + j); xr[j] -= T(sv.re); xi[j] -= T(sv.im); }
             }
         }
     }
@@ -605,13 +605,13 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             const int* gidx = dir ? J.ridx : J.cidx;
             const cx<double>* gval = dir ? J.rval : J.cval;
             for (int q = lane; q < n_ell; q += 64) {
-                s_eidx[q] = (unsigned char)gidx[q];
-                const cx<double> v = gval[q];
+                s_eidx[q] = (unsigned char)gload_s(gidx + q);
+                const cx<double> v = gload(gval + q);
                 s_eval[q] = cx<T>{T(v.re), T(v.im)};
             }
         }
-        const cx<double> z = J.z[e];
-        double u_next = act ? J.U[(size_t)(dir ? N - 1 : 0) * B + r] : 0.0;
+        const cx<double> z = gload(J.z + e);
+        double u_next = act ? gload_s(J.U + (size_t)(dir ? N - 1 : 0) * B + r) : 0.0;
         // the recursion state (y_n or x_n) is kept in the group's stage between steps
         stage_row<T, B>(zero_row<T, B>(), zero_row<T, B>(), g.stage, r, act);
         wave_sync();
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             const bool last = (s == N - 1);
             if (last && __all(!act || contour)) break;
             const double uu = u_next;
-            if (!last && act) u_next = J.U[(size_t)(dir ? N - 2 - s : s + 1) * B + r];
+            if (!last && act) u_next = gload_s(J.U + (size_t)(dir ? N - 2 - s : s + 1) * B + r);
             bool done64 = false;
             if constexpr (kF32) {
                 if (s == 0 || last) {       // rings 0 and N-1 carry Sigma: invert in FP64
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             }
             const int c = dir ? N - 2 - s : s;   // coupling block index
             const int slot = dir ? N - 2 - s : s + 1;
-            const int base = J.ell_map[c] * B * K;
+            const int base = gload_s(J.ell_map + c) * B * K;
             // P product: t[r][j] = sum_l X[r][l] P[l][j]
             //   fwd: P[l][j] = -H[l][j] (column-ELL);  bwd: P[l][j] = -conj(H[j][l]) (row-ELL)
             T tr[B], ti[B];
@@ -738,20 +738,20 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
                     const cx<T>* sb = reinterpret_cast<const cx<T>*>(S.store_b) + o_row;
                     if (n > 0) {
 #pragma unroll
-                        for (int j = 0; j < B; ++j) { const cx<T> v = sf[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                        for (int j = 0; j < B; ++j) { const cx<T> v = gload(sf + j); kr[j] -= v.re; ki[j] -= v.im; }
                     }
                     if (n < N - 1) {
 #pragma unroll
-                        for (int j = 0; j < B; ++j) { const cx<T> v = sb[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                        for (int j = 0; j < B; ++j) { const cx<T> v = gload(sb + j); kr[j] -= v.re; ki[j] -= v.im; }
                     }
-                    add_a_row<double, B>(J, e, n, r, J.U[(size_t)n * B + r], J.z[e], kr, ki);
+                    add_a_row<double, B>(J, e, n, r, gload_s(J.U + (size_t)n * B + r), gload(J.z + e), kr, ki);
                 }
                 Grp<double, B> g64{r, act64, s_stage64[gsafe], s_prow64[gsafe], s_keys[gsafe]};
                 gj_inverse<double, B>(kr, ki, g64);
                 if (act64) {
                     const cx<double> d = s_stage64[gsafe][r * B + r];
-                    reinterpret_cast<cx<T>*>(J.gr_diag)[(size_t)e * N * B + (size_t)n * B + r] =
-                        cx<T>{(T)d.re, (T)d.im};
+                    gstore(reinterpret_cast<cx<T>*>(J.gr_diag) + (size_t)e * N * B + (size_t)n * B + r,
+                           cx<T>{(T)d.re, (T)d.im});
                 }
                 wave_sync();
             }
@@ -767,18 +767,18 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             const cx<T>* sb = reinterpret_cast<const cx<T>*>(S.store_b) + o_row;
             if (n > 0) {
 #pragma unroll
-                for (int j = 0; j < B; ++j) { const cx<T> v = sf[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                for (int j = 0; j < B; ++j) { const cx<T> v = gload(sf + j); kr[j] -= v.re; ki[j] -= v.im; }
             }
             if (n < N - 1) {
 #pragma unroll
-                for (int j = 0; j < B; ++j) { const cx<T> v = sb[j]; kr[j] -= v.re; ki[j] -= v.im; }
+                for (int j = 0; j < B; ++j) { const cx<T> v = gload(sb + j); kr[j] -= v.re; ki[j] -= v.im; }
             }
-            add_a_row<T, B>(J, e, n, r, J.U[(size_t)n * B + r], J.z[e], kr, ki);
+            add_a_row<T, B>(J, e, n, r, gload_s(J.U + (size_t)n * B + r), gload(J.z + e), kr, ki);
         }
         gj_inverse<T, B>(kr, ki, g);
         if (act) {
             const cx<T> d = g.stage[r * B + r];
-            reinterpret_cast<cx<T>*>(J.gr_diag)[(size_t)e * N * B + (size_t)n * B + r] = d;
+            gstore(reinterpret_cast<cx<T>*>(J.gr_diag) + (size_t)e * N * B + (size_t)n * B + r, d);
         }
         wave_sync();
     }
