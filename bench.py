@@ -51,6 +51,18 @@ def ell_width(dev: W.Device) -> int:
     return K
 
 
+def is_circulant(M: np.ndarray) -> bool:
+    b = M.shape[0]
+    idx = (np.arange(b)[None, :] - np.arange(b)[:, None]) % b
+    return bool(np.array_equal(M, M[0][idx]))
+
+
+def lead_is_circulant(ld) -> bool:
+    """Every block of the lead ring-circulant: the library decimates it in ring modes."""
+    return (is_circulant(ld.tau) and all(is_circulant(m) for m in ld.h_diag)
+            and all(is_circulant(m) for m in ld.h_up))
+
+
 def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
     """Real flops per kernel launch, from the method's operation counts.
 
@@ -72,9 +84,17 @@ def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
     # repeats the inverse and adds tau g tau^H
     per_it = {1: 1 * inv + 6 * mul, 2: 8 * inv + 8 * mul}
     fin = {1: inv + 2 * mul, 2: 8 * inv + 2 * mul}
+    # ring-circulant leads are decimated as b scalar chains: per mode and doubling step
+    # about 68 flops (one-ring layer) or 115 (two-ring layer, closed-form 2x2 inverse);
+    # then per mode ~28 flops for g_s and Sigma_q and 8 b^2 for the back transform
+    per_it_modes = {1: 68.0 * b, 2: 115.0 * b}
+    fin_modes = 28.0 * b + 8.0 * b * b
     dec = 0.0
     for l, ld in enumerate((p.device.left, p.device.right)):
-        dec += per_it[ld.period] * float(decim_iters[:, l].sum()) + fin[ld.period] * len(decim_iters)
+        if lead_is_circulant(ld):
+            dec += per_it_modes[ld.period] * float(decim_iters[:, l].sum()) + fin_modes * len(decim_iters)
+        else:
+            dec += per_it[ld.period] * float(decim_iters[:, l].sum()) + fin[ld.period] * len(decim_iters)
     return {"recur": recur, "cdiag": cdiag, "column": column, "decimate": dec}
 
 
@@ -308,7 +328,7 @@ def measured_traffic(kernel: str, b: int, precision: str):
     src = os.path.join(ROOT, "paper_2407_14633_amd", "csrc", "negf_kernels.hpp")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     names = {"recur": f"negf::k_recur<double, {b}>", "cdiag": f"negf::k_cdiag<double, {b}>",
-             "column": f"negf::k_column<double, {b}>", "decimate": f"negf::k_decimate2<{b}>"}
+             "column": f"negf::k_column<double, {b}>", "decimate": f"negf::k_decimate_circ<{b}>"}
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
         for line in open(path):
             if line.startswith("machine-readable: "):
