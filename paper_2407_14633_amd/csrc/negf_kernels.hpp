@@ -134,7 +134,7 @@ __device__ __forceinline__ constexpr int gj_col(int t, int k) {
 // 1 / (re + i im) = conj / |.|^2, the form every pivot reciprocal uses.
 template <typename T>
 __device__ __forceinline__ void pivot_recip(T re, T im, T& qr, T& qi) {
-    const T inv_d = T(1) / (re * re + im * im);
+    const T inv_d = T(1) / fma(re, re, im * im);   // explicit fma: every kernel rounds alike
     qr = re * inv_d;
     qi = -im * inv_d;
 }
@@ -182,8 +182,8 @@ __device__ __forceinline__ void gj_inverse(T (&ar)[B], T (&ai)[B], const Grp<T, 
         const cx<T> q = g.prow[k];                                 // 1 / P_k
         const cx<T> q1 = g.prow[k + 1 < B ? k + 1 : k];
         // f = R_ik / P_k for the other rows, 0 for the pivot row
-        T fr = ar[k] * q.re - ai[k] * q.im;
-        T fi = ar[k] * q.im + ai[k] * q.re;
+        T fr = fma(ar[k], q.re, -(ai[k] * q.im));
+        T fi = fma(ar[k], q.im, ai[k] * q.re);
         fr = piv ? T(0) : fr;
         fi = piv ? T(0) : fi;
         // pivot bookkeeping without a branch (a branch would wait for q alone)
@@ -252,8 +252,8 @@ __device__ __forceinline__ void gj_inverse(T (&ar)[B], T (&ai)[B], const Grp<T, 
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             const T xr = ar[j], xi = ai[j];
-            ar[j] = xr * sr - xi * si;
-            ai[j] = xr * si + xi * sr;
+            ar[j] = fma(xr, sr, -(xi * si));
+            ai[j] = fma(xr, si, xi * sr);
         }
 #pragma unroll
         for (int j = 0; j < B; ++j) {
