@@ -69,6 +69,46 @@ def test_decimation_matches_oracle(gpu_lib, case):
                 assert abs(int(it[k]) - itr) <= 1, (it[k], itr)
 
 
+def _dimer_surface_stable(w, h0, h1):
+    """Retarded surface GF of the semi-infinite chain h0, h1, h0, ... (site energy in w):
+    the root of w|h1|^2 g^2 - (w^2 - |h0|^2 + |h1|^2) g + w = 0 with Im g < 0, the
+    larger root from the quadratic formula and the other from the product w / a, so
+    neither loses digits where w is tiny (E at the lead's on-site energy)."""
+    a = w * abs(h1) ** 2
+    bq = -(w * w - abs(h0) ** 2 + abs(h1) ** 2)
+    disc = np.sqrt(bq * bq - 4 * a * w + 0j)
+    r_p, r_m = -bq + disc, -bq - disc
+    big = (r_m if abs(r_m) >= abs(r_p) else r_p) / (2 * a)
+    small = (w / a) / big
+    cand = [r for r in (big, small) if r.imag < 0]
+    assert len(cand) == 1, (big, small)
+    return cand[0]
+
+
+@pytest.mark.parametrize("n", [8, 17])
+def test_ring_mode_decimation_exact_at_lead_pole(gpu_lib, n):
+    """At E = U_lead a zigzag ring block z - U is nearly zero: the dense two-ring
+    layer inversion loses digits there (the oracle's too).  Per ring mode the lead is a
+    dimer chain with a closed-form surface GF, Sigma = F diag(t^2 g_q) F^H; the
+    ring-mode decimation must match it to rounding level at and next to the pole."""
+    dev = W.zigzag_cnt(n, 4)
+    q = np.arange(n)
+    F = np.exp(2j * np.pi * np.outer(np.arange(n), q) / n) / np.sqrt(n)
+    with gpu_lib.NegfDevice(dev) as d:
+        for U_L, U_R in ((0.07, -0.03), (0.0, 0.0)):
+            d.set_potential(np.zeros(dev.n_rings * dev.b), U_L, U_R)
+            for lead, U in ((0, U_L), (1, U_R)):
+                z = np.array([U + 1e-6j, U + 3e-4 + 1e-6j, U - 2e-5 + 1e-6j, 0.3 + 1e-6j])
+                sig, _ = d.lead_self_energy(lead, z)
+                for k, zk in enumerate(z):
+                    g = [_dimer_surface_stable(zk - U, W.T_CC * (1 + np.exp(-2j * np.pi * m / n)), W.T_CC)
+                         for m in q]
+                    ref = F @ np.diag(W.T_CC ** 2 * np.array(g)) @ F.conj().T
+                    err = rel(sig[k], ref)
+                    say(f"  n={n} lead {lead} U={U} z={zk}: rel {err:.2e}")
+                    assert err < 1e-11, (n, lead, zk, err)
+
+
 def test_decimation_no_convergence_is_reported(gpu_lib):
     dev = W.zigzag_cnt(8, 4)
     with gpu_lib.NegfDevice(dev, decim_max_iter=2) as d:
