@@ -17,7 +17,9 @@
 // job's results are bit-identical alone and in a batch.
 //
 // Kernels (see the host side for launch shapes):
-//   k_decimate   lead self-energies by Sancho-Rubio layer doubling, FP64,
+//   k_decimate_circ  lead self-energies of ring-circulant leads: Sancho-Rubio
+//                layer doubling per ring Fourier mode (scalar chains), FP64
+//   k_decimate   lead self-energies by dense Sancho-Rubio layer doubling, FP64,
 //   k_decimate2  one-ring (k_decimate) and two-ring (k_decimate2) principal layers
 //   k_recur      left- and right-connected recursions (Algorithm 2), one chain
 //                per (node, direction); stores y~/x~ (real axis) or y/x
