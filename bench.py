@@ -173,8 +173,10 @@ def batch_flops(ps) -> dict:
     return tot
 
 
-def run_batch(ps, precision: int, steps: int, warmup: int, grid_scale: int = 0):
-    """Times negf_batch_solve_dev over all problems of the batch, inputs resident in HBM."""
+def run_batch(ps, precision: int, steps: int, warmup: int, grid_scale: int = 0, autotune: bool = False,
+              graph: bool = False):
+    """Times negf_batch_solve_dev over all problems of the batch, inputs resident in HBM;
+    optionally after the schedule autotuner, and as replays of a captured HIP graph."""
     import torch
     from paper_2407_14633_amd import negf
     dev = torch.device("cuda:0")
@@ -198,6 +200,11 @@ def run_batch(ps, precision: int, steps: int, warmup: int, grid_scale: int = 0):
     if grid_scale:
         ws.set_grid_scale(grid_scale)
     stream = torch.cuda.current_stream()
+    schedule = None
+    if autotune:
+        best = ws.autotune(jobs, stream, reps=1)
+        schedule = {"grid_scale": best.grid_scale, "order": best.order, "ms_per_solve": round(best.ms_per_solve, 2)}
+        log(f"  autotuned schedule {schedule}")
     for _ in range(warmup):
         ws.solve_dev(jobs, stream)
     ws.sync()
@@ -212,8 +219,23 @@ def run_batch(ps, precision: int, steps: int, warmup: int, grid_scale: int = 0):
     times = ws.kernel_times()
     out = dict(ms_per_step=1e3 * dt / steps, times=times, hbm_bytes=ws.bytes(),
                current=[float(j["current"].item()) for j in jobs],
-               charge=[j["charge"].cpu().numpy() for j in jobs])
+               charge=[j["charge"].cpu().numpy() for j in jobs], schedule=schedule)
     ws.close()
+    if graph:
+        # the same batch recorded once into a HIP graph (private workspace), replayed
+        gstream = torch.cuda.Stream()   # capture needs a created stream (default priority)
+        torch.cuda.synchronize()
+        with negf.Graph(jobs, gstream) as gph:
+            gph.launch(gstream)
+            gph.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                gph.launch(gstream)
+            torch.cuda.synchronize()
+            out["graph_ms_per_step"] = 1e3 * (time.perf_counter() - t0) / steps
+            gph.sync()
+        log(f"  graph replay ms/step {out['graph_ms_per_step']:.2f}")
     for d in devs:
         d.close()
     return out
@@ -231,12 +253,13 @@ def bench_batch(a):
     for name, prec, peak in (("f64", negf.FP64, FP64_PEAK_TFLOPS), ("f32_bulk", negf.FP32_BULK, FP32_PEAK_TFLOPS)):
         if name == "f32_bulk" and a.no_fp32:
             continue
-        r = run_batch(ps, prec, a.steps, a.warmup)
+        r = run_batch(ps, prec, a.steps, a.warmup, autotune=not a.no_autotune, graph=not a.no_graph)
         ms, calls = r["times"]["recur"]
         per_step = ms / a.steps          # a batch step runs one recursion launch per store chunk
         ach = flops["recur"] / (per_step * 1e-3) / 1e12
         log(f"batch {name} ms/step {r['ms_per_step']:.2f} kernels {r['times']} HBM workspace {r['hbm_bytes'] / 2**30:.1f} GiB")
-        res[name] = dict(r=r, value=n_e / (r["ms_per_step"] * 1e-3),
+        res[name] = dict(r=r, value=n_e / (r["ms_per_step"] * 1e-3), schedule=r["schedule"],
+                         graph_ms_per_step=r.get("graph_ms_per_step"),
                          roofline={"kernel": "recur", "bound": "alu", "achieved": round(ach, 4), "peak": peak,
                                    "unit": "TFLOP/s", "frac": round(ach / peak, 5), "traffic": None,
                                    "ms_per_step": round(per_step, 4), "launches_per_step": calls // a.steps,
@@ -257,6 +280,7 @@ def bench_batch(a):
             # and the largest |I32 - I64| relative to that largest current
             **_current_diffs(res["f32_bulk"]["r"]["current"], r64["r"]["current"])},
         "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in r64["r"]["times"].items()},
+        "schedule": r64["schedule"], "graph_ms_per_step": r64["graph_ms_per_step"],
         "serving": None,
     }
     print(json.dumps(line), flush=True)
@@ -364,6 +388,8 @@ def main():
     ap.add_argument("--requests", type=int, default=8, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=10.0, help="serving: Poisson arrival rate (req/s)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="batch: skip the schedule autotuner")
+    ap.add_argument("--no-graph", action="store_true", help="batch: skip the HIP-graph replay timing")
     ap.add_argument("--serving-fp32", action="store_true", help="serving: FP32-bulk NEGF instead of FP64")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
