@@ -398,9 +398,9 @@ def main():
         calibrate_copy(a.calibrate_copy)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the energy-point solve on a single MI355X "
-              "(energy nodes would shard across GPUs with one all-reduce of the charge; not built here).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each energy-point solve on a single MI355X "
+              "(energy nodes would shard across GPUs with one all-reduce of the charge; that path is not "
+              "implemented).", file=sys.stderr)
         raise SystemExit(2)
     from paper_2407_14633_amd import negf
     if a.workload == "batch":
