@@ -109,6 +109,60 @@ def test_ring_mode_decimation_exact_at_lead_pole(gpu_lib, n):
                     assert err < 1e-11, (n, lead, zk, err)
 
 
+def _circulant(row):
+    b = len(row)
+    return np.array([[row[(j - i) % b] for j in range(b)] for i in range(b)], np.complex128)
+
+
+def _random_circulant_device(N, b, seed, periods=(1, 2)):
+    """Random ring-circulant device and leads (Hermitian circulant on-site blocks)."""
+    rng = np.random.default_rng(seed)
+
+    def herm():
+        c = 0.6 * (rng.normal(size=b) + 1j * rng.normal(size=b))
+        c = 0.5 * (c + np.conj(c[(-np.arange(b)) % b]))   # c_k = conj(c_{-k}): Hermitian
+        return _circulant(c)
+
+    def gen():
+        return _circulant(0.6 * (rng.normal(size=b) + 1j * rng.normal(size=b)))
+
+    def lead(period):
+        return W.Lead(period=period, h_diag=np.stack([herm() for _ in range(period)]),
+                      h_up=np.stack([gen() for _ in range(period)]), tau=gen())
+
+    return W.Device(h_diag=np.stack([herm() for _ in range(N)]), h_up=np.stack([gen() for _ in range(N - 1)]),
+                    left=lead(periods[0]), right=lead(periods[1]))
+
+
+@pytest.mark.parametrize("periods,b", [((1, 1), 5), ((1, 2), 6), ((2, 2), 4)])
+def test_ring_mode_decimation_generic_circulant_leads(gpu_lib, periods, b):
+    """Ring-mode decimation on random circulant leads of one- and two-ring layers
+    (complex couplings), per node against the oracle's dense decimation, and a full
+    solve of the circulant device against the oracle."""
+    dev = _random_circulant_device(5, b, seed=40 + b, periods=periods)
+    z = np.array([0.3 + 1e-4j, -0.9 + 1e-4j, 1.7 + 1e-3j, 0.8 + 0.4j, -2.0 + 1.5j])
+    with gpu_lib.NegfDevice(dev) as d:
+        d.set_potential(np.zeros(dev.n_rings * dev.b), 0.05, -0.02)
+        for lead, ld, Ul in ((0, dev.left, 0.05), (1, dev.right, -0.02)):
+            sig, it = d.lead_self_energy(lead, z)
+            for k, zk in enumerate(z):
+                ref, itr = O.self_energy(ld, Ul, zk)
+                tol = max(1e-10, 20 * _oracle_sensitivity(ld, Ul, zk, ref))
+                assert rel(sig[k], ref) < tol, (periods, lead, zk, rel(sig[k], ref), tol)
+                assert abs(int(it[k]) - itr) <= 2, (it[k], itr)
+    rng = np.random.default_rng(b)
+    U = rng.uniform(-0.2, 0.2, dev.n_rings * dev.b)
+    bias = W.Bias(0.15, -0.1, 0.05, 0.04)
+    grid = W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 6, 7)
+    p = W.Problem("circ", dev, U, 0.02, -0.04, bias, grid, eta=1e-4)
+    ref = O.solve(p)
+    got = gpu_lib.solve_problem(p)
+    say("circulant device", periods, b, rel(got.charge, ref["charge"]), rel(got.T, ref["T"], floor=1e-12))
+    assert rel(got.charge, ref["charge"]) < 1e-10
+    assert rel(got.T, ref["T"], floor=1e-12) < 1e-9
+    assert abs(got.current - ref["current"]) <= 1e-10 * abs(ref["current"]) + 1e-25
+
+
 def test_decimation_no_convergence_is_reported(gpu_lib):
     dev = W.zigzag_cnt(8, 4)
     with gpu_lib.NegfDevice(dev, decim_max_iter=2) as d:
