@@ -304,6 +304,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
             D.tau[l] = d->lead[l].tau;
             D.lmodes[l] = d->lead[l].circ ? d->lead[l].modes : nullptr;
         }
+        D.sigma_circ = (D.lmodes[0] && D.lmodes[1] && w->circ_decimation) ? 1 : 0;
         negf::RedJob& R = rj[i];
         R.Nb = d->N * d->b;
         R.n_c = J.n_c + J.n_poles;

@@ -367,6 +367,28 @@ __device__ __forceinline__ T row_quad_pipe(const T (&xr)[B], const T (&xi)[B], c
     return acc;
 }
 
+// row_quad_pipe for a circulant Y (Y[k][j] = Y[0][(j - k) mod B]): its first row is
+// read once into registers and the B*B products take no further LDS reads.
+template <typename T, int B>
+__device__ __forceinline__ T row_quad_circ(const T (&xr)[B], const T (&xi)[B], const cx<T>* Y) {
+    T gr[B], gi[B];
+#pragma unroll
+    for (int d = 0; d < B; ++d) { const cx<T> y = Y[d]; gr[d] = y.re; gi[d] = y.im; }
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+        T vr = T(0), vi = T(0);
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int d = (j - k + B) % B;
+            vr = fma(xr[k], gr[d], fma(-xi[k], gi[d], vr));
+            vi = fma(xr[k], gi[d], fma(xi[k], gr[d], vi));
+        }
+        acc = fma(vr, xr[j], fma(vi, xi[j], acc));
+    }
+    return acc;
+}
+
 // out = X[r,:] * Y with both operands in LDS; the k loop is not unrolled so the
 // code stays small (used by the decimation's op sequence).
 template <typename T, int B>
@@ -430,6 +452,7 @@ struct JobDesc {
     // ring-circulant leads: per lead [5][b] eigenvalues of D_0, D_{P-1}, h_up[0],
     // h_up[P-1], tau on the ring Fourier vectors (lead potential included); null otherwise
     const cx<double>* lmodes[2];
+    int sigma_circ;               // Sigma from the ring-mode decimation: exactly circulant
 };
 
 // A span: the nodes [e0, e0+cnt) of one job that one kernel launch covers
@@ -809,6 +832,8 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
     while (next_unit<G>(S, u)) {
         const JobDesc& J = S.jobs[u.job];
         const int lead = u.side;
+        // Sigma of this lead came from the ring-mode decimation and is exactly circulant
+        const bool gcirc = J.lmodes[lead] != nullptr && J.sigma_circ;
         const bool act = (gi < G) && (gi < u.cnt);
         const int N = J.N;
         const int e = u.e0 + (act ? gi : 0);     // node index within the job (>= n_c)
@@ -851,9 +876,12 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j]).  Gamma does not
             // change along the chain; its offset is made opaque each step so that its
             // B*B reads are not hoisted out of the loop into (spilled) registers.
+            // For a ring-circulant lead (Sigma, hence Gamma, circulant by construction of the
+            // ring-mode decimation) only Gamma's first row is read.
             int goff = gsafe * B * B;
             asm volatile("" : "+v"(goff));
-            const T acc = row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
+            const T acc = gcirc ? row_quad_circ<T, B>(wr, wi, &s_gam[0][0] + goff)
+                                : row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
             if (act) gstore_s(aout + (size_t)n * B + r, acc);
             if (s == N - 1) break;
             // W_next[r][:] = -sum_k P[r][k] W[k][:],  P = y~_n (right) or x~_n (left)
