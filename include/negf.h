@@ -245,7 +245,10 @@ negf_status negf_workspace_set_order(negf_workspace *w, int order);
  * chains per node, and Sigma is transformed back; its stopping test applies
  * decim_tol to the mode values of alpha and beta, which bound every entry, so
  * it stops at the same step as the dense test or later.  0: every lead uses
- * the dense b x b (or 2b x 2b) layer. */
+ * the dense b x b (or 2b x 2b) layer.  With ring modes Sigma is exactly
+ * circulant and the lead-column kernel reads only the first row of Gamma; a job
+ * that reuses a self-energy cache (sigma_mode 2) should run with the basis the
+ * cache was filled with (otherwise its results move at the rounding level). */
 negf_status negf_workspace_set_lead_basis(negf_workspace *w, int ring_modes);
 /* Times every schedule setting on this job list (reps solves each, device
  * pointers, on hip_stream), keeps the fastest in w and returns it in *best. */
