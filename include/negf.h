@@ -273,7 +273,7 @@ negf_status negf_graph_sync(negf_graph *g, int *failed_job);
 void negf_graph_destroy(negf_graph *g);
 
 /* ------------------------------------------------ semi-adaptive grid ----
- * Section 4 (number of integration points): the real-axis window [E_min, E_max]
+ * Section 3.3 (number of integration points): the real-axis window [E_min, E_max]
  * (Eq. 4, f1 = f2 = 14) is split at E_l1 < E_l2 into three parts, each integrated
  * by Gauss-Legendre with density[p] nodes per kT_min (at least one node).  The
  * integrand f_L A_L + f_R A_R summed over the atoms of ring N/2 is evaluated on
@@ -289,7 +289,7 @@ negf_status negf_semi_adaptive_grid(negf_device *d, const negf_bias *bias, doubl
                                     double *E_r, double *w_r, int cap, int *n_r, double *limits);
 
 /* --------------------------------------------------------- mode space ----
- * Section 2.1 and Section 2.2.3: a tube in the mode-space representation, one
+ * Section 2.2.2 (blocks as scalars or arrays of modes): a tube in the mode-space representation, one
  * scalar chain per ring mode.  Every ring block (h_diag, h_up, lead blocks, tau)
  * must be circulant, H[i][j] = H[0][(j - i) mod b], and the potential uniform on
  * each ring; then mode q sees the scalar lambda_q(C) = sum_k C[0][k] e^{2 pi i qk/b}
@@ -312,7 +312,7 @@ negf_status negf_modes_solve(negf_modes *m, negf_workspace *w, const negf_bias *
 void negf_modes_destroy(negf_modes *m);
 
 /* ------------------------------------------------------------ serving ----
- * Self-consistent bias points (Section 2.4, Algorithm 3) served with continuous
+ * Self-consistent bias points (Section 2.3, Algorithm 3) served with continuous
  * batching.  A request is a device with flat leads, a bias point and a fixed
  * energy grid.  The server iterates
  *     rho_in -> Poisson -> U -> NEGF (batched with every running request) -> rho_out

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
 with the HIP library.
 
-The paper's semi-adaptive scheme (Section 4, discussion of integration points),
+The paper's semi-adaptive scheme (Section 3.3, discussion of integration points),
 in its order:
 1. the window [E_min, E_max] (Eq. 4) is split at E_l1 < E_l2 into three parts,
    each integrated by Gauss-Legendre with a user density of nodes per kT;

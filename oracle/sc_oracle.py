@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
 with the HIP library.
 
-What it computes (paper Section 2.4 and Algorithm 3, with the electrostatics
+What it computes (paper Section 2.3 and Algorithm 3, with the electrostatics
 reduced to one dimension along the tube axis):
 
 * ``poisson_rings``: the per-ring electrostatic potential phi from the per-ring

@@ -237,7 +237,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         gr += (size_t)ncz * Nb;
         ad += (size_t)jobs[i].n_r * 2 * Nb;
         nodes += ne;
-        sig += (size_t)ne * 2 * b2;
+        if (!jobs[i].sigma_mode) sig += (size_t)ne * 2 * b2;   // otherwise the job's own cache holds them
         part += (size_t)negf::RED_SEGS * Nb;
         max_ne = std::max(max_ne, ne);
         max_nb = std::max(max_nb, (int)Nb);

@@ -1,4 +1,4 @@
-// Semi-adaptive real-axis grid (Section 4, on the number of integration points):
+// Semi-adaptive real-axis grid (Section 3.3, on the number of integration points):
 // the window [E_min, E_max] of Eq. 4 is split at E_l1 < E_l2 into three parts,
 // each integrated by Gauss-Legendre with its own density of nodes per kT; the
 // integrand f_L A_L + f_R A_R at the centre of the channel (ring N/2, atoms

@@ -1,5 +1,5 @@
-// Mode-space solves (Section 2.1: the CNT in the mode-space approximation; Section
-// 2.2.3: blocks that are single numbers, one per mode).
+// Mode-space solves (Section 2.2.2: the CNT in the mode-space approximation, with blocks
+// that are single numbers, one per mode).
 //
 // When every ring block is circulant (H[i][j] depends only on (j - i) mod b, as
 // for a nanotube ring whose atoms are related by the rotation symmetry) and the

@@ -1,5 +1,5 @@
 // Self-consistency kernel of the serving loop: per request, one workgroup
-// turns the NEGF charge into the next potential (Section 2.4, Algorithm 3):
+// turns the NEGF charge into the next potential (Section 2.3, Algorithm 3):
 //   rho_out_j = sum_i charge_{j,i}                     electrons per ring
 //   Broyden's modified second method on rho (f = rho_in - rho_out)
 //   1-D finite-difference Poisson along the axis with a coaxial gate:

@@ -91,7 +91,7 @@ struct negf_server {
     std::condition_variable cv_work, cv_done;
     bool stop = false;
     std::deque<ScJob*> pending;
-    std::vector<ScJob*> running;
+    std::vector<ScJob*> running;  // written by the server thread under mu, read by it freely
     std::map<long long, ScJob*> jobs;
     long long next_id = 1;
     negf_status fatal = NEGF_OK;
@@ -247,6 +247,7 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
                            S->d_reqs, 0);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(S->stream));
+        std::lock_guard<std::mutex> lk(S->mu);   // negf_server_stats reads the running set
         for (ScJob* j : fresh) S->running.push_back(j);
     }
     if (S->running.empty()) return NEGF_OK;
@@ -268,7 +269,10 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
                           hipMemcpyDeviceToHost, S->stream));
     HIPCHK(hipEventRecord(S->ws->done, S->stream));
     HIPCHK(hipStreamSynchronize(S->stream));   // rq stays alive until the upload has run
-    S->passes++;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->passes++;
+    }
     // per-request NEGF flags (bit 1: decimation, bit 2: non-finite result)
     std::vector<ScJob*> keep;
     for (size_t k = 0; k < S->running.size(); ++k) {
@@ -289,7 +293,10 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
             keep.push_back(j);
         }
     }
-    S->running.swap(keep);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->running.swap(keep);
+    }
     S->ws->last_n_jobs = 0;
     return NEGF_OK;
 }
@@ -324,8 +331,12 @@ void server_loop(negf_server* S) {
         if (st != NEGF_OK) {
             // a HIP or allocation failure: fail the running requests and keep serving
             const std::string msg = g_err;
-            for (ScJob* j : S->running) finish_job(S, j, st);
-            S->running.clear();
+            std::vector<ScJob*> failed;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                failed.swap(S->running);
+            }
+            for (ScJob* j : failed) finish_job(S, j, st);
             std::lock_guard<std::mutex> lk(S->mu);
             S->fatal = st;
             S->fatal_msg = msg;

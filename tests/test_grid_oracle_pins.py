@@ -38,3 +38,78 @@ def test_refinement_follows_the_peak():
     assert Es == E_p[np.argmin(np.abs(E_p - peak))]
     assert l1 == pytest.approx(-0.2 - 3 * kT, abs=1e-15) and l2 == pytest.approx(Es + kT, abs=1e-15)
     assert np.sum(w_r) == pytest.approx(G.window(bias)[1] - G.window(bias)[0], rel=1e-13)
+
+
+def _dense_spectral(prob, E):
+    """A_L, A_R diagonals at E + i eta from a dense inverse of M (the plain definition,
+    Eq. 2-3), independent of the oracle's banded route."""
+    from oracle import negf_oracle as O
+    z = E + 1j * prob.eta
+    sL, _ = O.self_energy(prob.device.left, prob.U_left, z)
+    sR, _ = O.self_energy(prob.device.right, prob.U_right, z)
+    N, b = prob.device.n_rings, prob.device.b
+    H = np.zeros((N * b, N * b), np.complex128)
+    for j in range(N):
+        H[j * b:(j + 1) * b, j * b:(j + 1) * b] = prob.device.h_diag[j]
+        if j + 1 < N:
+            H[j * b:(j + 1) * b, (j + 1) * b:(j + 2) * b] = prob.device.h_up[j]
+            H[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = prob.device.h_up[j].conj().T
+    S = np.zeros_like(H)
+    S[:b, :b] += sL
+    S[-b:, -b:] += sR
+    G = np.linalg.inv(z * np.eye(N * b) - H - np.diag(prob.U) - S)
+    gL = np.zeros_like(H)
+    gR = np.zeros_like(H)
+    gL[:b, :b] = 1j * (sL - sL.conj().T)
+    gR[-b:, -b:] = 1j * (sR - sR.conj().T)
+    AL = np.real(np.diag(G @ gL @ G.conj().T))
+    AR = np.real(np.diag(G @ gR @ G.conj().T))
+    return G, AL, AR
+
+
+def _tiny_biased_problem(eta=1e-3):
+    # 5 rings: N // 2 = 2 is not a mirror image of any other ring under the
+    # asymmetric potential; unequal temperatures keep f_L and f_R apart everywhere
+    n, N = 4, 5
+    dev = W.zigzag_cnt(n, N)
+    U = np.linspace(-0.12, 0.2, N * n) + 0.03 * np.sin(np.arange(N * n))
+    bias = W.Bias(0.2, -0.1, 0.03, 0.05)
+    grid = W.EnergyGrid(np.zeros(0, complex), np.zeros(0, complex), np.zeros(0), np.zeros(0))
+    return W.Problem("tiny", dev, U, 0.0, 0.0, bias, grid, eta=eta)
+
+
+def test_centre_integrand_matches_dense_inverse():
+    """f_L A_L + f_R A_R summed over ring N // 2 against a dense inverse, with the
+    Fermi functions evaluated here from their definition (Eq. 3-4)."""
+    p = _tiny_biased_problem()
+    E = np.array([-0.7, -0.2, 0.05, 0.13, 0.9, 1.4])
+    got = G.centre_integrand(p, E)
+    N, b, jc = p.device.n_rings, p.device.b, p.device.n_rings // 2
+    fd = lambda x, mu, kT: 1.0 / (1.0 + np.exp((x - mu) / kT))
+    for k, Ek in enumerate(E):
+        _, AL, AR = _dense_spectral(p, Ek)
+        ring = slice(jc * b, (jc + 1) * b)
+        want = fd(Ek, p.bias.mu_L, p.bias.kT_L) * AL[ring].sum() + fd(Ek, p.bias.mu_R, p.bias.kT_R) * AR[ring].sum()
+        assert got[k] == pytest.approx(want, rel=1e-10, abs=1e-14), (Ek, got[k], want)
+        # the integrand picks ring N // 2 only: its neighbours give other values
+        for other in (jc - 1, jc + 1):
+            o = slice(other * b, (other + 1) * b)
+            alt = fd(Ek, p.bias.mu_L, p.bias.kT_L) * AL[o].sum() + fd(Ek, p.bias.mu_R, p.bias.kT_R) * AR[o].sum()
+            assert abs(alt - want) > 1e-6 * abs(want)
+
+
+def test_centre_integrand_equilibrium_sum_rule():
+    """At mu_L = mu_R and equal kT the integrand is f(E) times the ring's spectral
+    weight, i (G - G^H) - 2 eta G G^H on the diagonal (the sum rule
+    A = A_L + A_R + 2 eta G G^H), which involves no broadening matrix at all."""
+    p = _tiny_biased_problem(eta=2e-2)
+    p.bias = W.Bias(0.04, 0.04, 0.05, 0.05)
+    E = np.array([-1.1, -0.3, 0.02, 0.6])
+    got = G.centre_integrand(p, E)
+    b, jc = p.device.b, p.device.n_rings // 2
+    for k, Ek in enumerate(E):
+        Gm, _, _ = _dense_spectral(p, Ek)
+        A = np.real(np.diag(1j * (Gm - Gm.conj().T) - 2 * p.eta * Gm @ Gm.conj().T))
+        f = 1.0 / (1.0 + np.exp((Ek - 0.04) / 0.05))
+        want = f * A[jc * b:(jc + 1) * b].sum()
+        assert got[k] == pytest.approx(want, rel=1e-9, abs=1e-13), (Ek, got[k], want)
