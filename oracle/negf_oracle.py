@@ -210,9 +210,32 @@ def transmission(G0N, gam_L, gam_R):
 
 # ----------------------------------------------------------- occupations ----
 def fermi(E, mu, kT):
-    """Real Fermi function 1/(1+exp((E-mu)/kT)), overflow-safe."""
+    """Real Fermi function 1/(1+exp((E-mu)/kT)), overflow-safe and to full
+    relative precision on both sides (exp(-x)/(1+exp(-x)) for x > 0)."""
     x = (np.asarray(E, np.float64) - mu) / kT
-    return 0.5 * (1.0 - np.tanh(0.5 * x))
+    e = np.exp(-np.abs(x))
+    return np.where(x > 0, e, 1.0) / (1.0 + e)
+
+
+def fermi_difference(E, mu_L, kT_L, mu_R, kT_R):
+    """f_L(E) - f_R(E) of Eq. 5 without cancellation.
+
+    With x_l = (E - mu_l)/kT_l the identity
+        f(x_L) - f(x_R) = -expm1(x_L - x_R) f(x_L) f(-x_R)
+    holds exactly (f(-x) = 1 - f(x)); every factor is computed to full relative
+    precision, where the plain difference of two Fermi factors close to 1 (E far
+    below both levels, where in-band transmissions are of order one) loses all
+    but a few digits.  Beyond |x_L - x_R| > 700 the factors are far apart and the
+    plain difference is used.
+    """
+    E = np.asarray(E, np.float64)
+    xL = (E - mu_L) / kT_L
+    xR = (E - mu_R) / kT_R
+    d = xL - xR
+    far = np.abs(d) > 700.0
+    dd = np.where(far, 0.0, d)
+    out = -np.expm1(dd) * fermi(E, mu_L, kT_L) * fermi(-E, -mu_R, kT_R)
+    return np.where(far, fermi(E, mu_L, kT_L) - fermi(E, mu_R, kT_R), out)
 
 
 def fermi_complex(z, mu, kT):
@@ -267,7 +290,8 @@ def reduce_energies(prob, gr_diag, AL, AR, T):
         fL = fermi(g.E_r, b.mu_L, b.kT_L)
         fR = fermi(g.E_r, b.mu_R, b.kT_R)
         charge += (1.0 / (2 * np.pi)) * ((g.w_r * fL)[:, None] * AL + (g.w_r * fR)[:, None] * AR).sum(axis=0)
-        current = prob.g_s * G0_PER_SPIN * float(np.sum(g.w_r * T * (fL - fR)))
+        dF = fermi_difference(g.E_r, b.mu_L, b.kT_L, b.mu_R, b.kT_R)
+        current = prob.g_s * G0_PER_SPIN * float(np.sum(g.w_r * T * dF))
     return prob.g_s * charge, current
 
 

@@ -37,6 +37,19 @@ __device__ __forceinline__ double fermi_real(double E, double mu, double kT) {
     return 1.0 / (1.0 + exp(x));
 }
 
+// f_L(E) - f_R(E) (Eq. 5) as -expm1(x_L - x_R) f(x_L) f(-x_R), an identity whose
+// factors all keep full relative precision; the plain difference of two Fermi
+// factors close to 1 (E far below both levels, where in-band transmissions are
+// of order one) keeps only a few digits.  Beyond |x_L - x_R| > 700 the plain
+// difference is exact enough and the exponential would overflow.
+__device__ __forceinline__ double fermi_diff(double E, double mu_L, double kT_L, double mu_R, double kT_R) {
+    const double xL = (E - mu_L) / kT_L, xR = (E - mu_R) / kT_R;
+    const double d = xL - xR;
+    const double fl = fermi_real(E, mu_L, kT_L);
+    if (fabs(d) > 700.0) return fl - fermi_real(E, mu_R, kT_R);
+    return -expm1(d) * fl * fermi_real(-E, -mu_R, kT_R);
+}
+
 __device__ __forceinline__ cx<double> fermi_cplx(cx<double> z, double mu, double kT) {
     // 1/(1 + exp(u)), u = (z - mu)/kT, evaluated through exp(-u) when Re u > 0
     const double ur = (z.re - mu) / kT, ui = z.im / kT;
@@ -94,7 +107,7 @@ __global__ void k_coef(const RedJob* jobs) {
         const double ch = cosh(fmin(fabs(x), 350.0));
         R.coef_r[4 * q + 0] = w * fl;
         R.coef_r[4 * q + 1] = w * fr;
-        R.coef_r[4 * q + 2] = w * (fl - fr);
+        R.coef_r[4 * q + 2] = w * fermi_diff(R.E_r[q], R.mu_L, R.kT_L, R.mu_R, R.kT_R);
         R.coef_r[4 * q + 3] = w / (4.0 * R.kT_L * ch * ch);
     }
     if (e < R.n_c + R.n_r && R.status[e]) {

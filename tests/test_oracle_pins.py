@@ -431,3 +431,27 @@ def test_reduction_matches_dense_density_matrix():
         cur += w * np.real(np.trace(gl @ G @ gr @ G.conj().T)) * (fL - fR)
     np.testing.assert_allclose(r["charge"], 2.0 * acc, rtol=1e-10, atol=1e-13)
     assert abs(r["current"] - 2.0 * O.G0_PER_SPIN * cur) <= 1e-8 * abs(r["current"])
+
+
+def test_fermi_functions_full_relative_precision():
+    """f and f_L - f_R (Eq. 5) against 50-digit evaluations, far into both tails,
+    where the plain difference of two Fermi factors close to 1 loses its digits."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    E = np.concatenate([np.linspace(-1.2, 1.2, 97), [-0.62109375, 0.05, -0.05, 0.0, 1e-9]])
+    for (muL, kTL, muR, kTR) in ((0.05, 0.0259, -0.05, 0.0259), (0.15, 0.0259, -0.15, 0.0259),
+                                 (0.3, 0.05, -0.1, 0.08), (0.0, 0.0259, 0.0, 0.0259)):
+        f = O.fermi(E, muL, kTL)
+        d = O.fermi_difference(E, muL, kTL, muR, kTR)
+        for k, e in enumerate(E):
+            fe = 1 / (1 + mp.exp((mp.mpf(e) - mp.mpf(muL)) / mp.mpf(kTL)))
+            fr = 1 / (1 + mp.exp((mp.mpf(e) - mp.mpf(muR)) / mp.mpf(kTR)))
+            # rounding of x = (E - mu)/kT itself moves exp(x) by ~|x| ulp
+            xs = abs(e - muL) / kTL + abs(e - muR) / kTR
+            assert abs(f[k] - float(fe)) <= 1.2e-16 * (4 + xs) * float(fe)
+            exact = float(fe - fr)
+            # and x_L - x_R carries the rounding of both, relative to its own size
+            dx = abs((e - muL) / kTL - (e - muR) / kTR)
+            assert abs(d[k] - exact) <= 1.2e-16 * (8 + 4 * xs * max(1.0, 1.0 / max(dx, 1e-300))) * abs(exact) + 1e-300
+    # equal levels: no current, exactly
+    assert np.all(O.fermi_difference(E, 0.1, 0.03, 0.1, 0.03) == 0.0)
