@@ -151,6 +151,29 @@ negf_status negf_solve_dev(negf_device *d, const negf_bias *bias,
 negf_status negf_sync(negf_device *d);
 
 /*
+ * Allocation-free form of negf_solve_dev, for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts, asynchrony and
+ * results as negf_solve_dev (status through negf_sync); no hipMalloc, hipFree or
+ * other allocating call is made.  Every work buffer (self-energies, per-node
+ * diagonals, recursion stores, schedule tables, counters) is placed in one fixed
+ * device area of negf_static_scratch_bytes() bytes (512 MiB) that the library
+ * holds on each GPU it runs on until the process ends; node ranges whose
+ * recursion stores do not fit next to the per-node arrays run in several chunks.
+ * EINVAL, with the sizes in the message, when the per-node arrays plus one
+ * node's stores exceed the area.  All calls on one GPU share the area, which
+ * keeps the last call's contents: calls that overlap on one GPU (other handles,
+ * other streams) race and must be serialised by the caller.
+ */
+negf_status negf_solve_dev_static(negf_device *d, const negf_bias *bias,
+                                  int n_c, const negf_c64 *z_c, const negf_c64 *w_c,
+                                  int n_r, const double *E_r, const double *w_r,
+                                  double *charge, double *T, double *current, void *hip_stream);
+
+/* Size in bytes of the fixed device area of negf_solve_dev_static. */
+size_t negf_static_scratch_bytes(void);
+
+/*
  * Lead self-energies alone (decimation, Eq. 2), host pointers, synchronous:
  * sigma[n][b][b] = Sigma_lead(z[k]), iters[n] = doubling steps (may be NULL).
  * Contour-style nodes: z is used as given (no eta is added).

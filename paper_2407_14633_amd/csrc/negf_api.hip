@@ -74,7 +74,23 @@ negf_status wait_prev(negf_workspace* w) {
     return NEGF_OK;
 }
 
+// Arena mode: the next 256-byte-aligned piece of the caller's fixed area.
+negf_status carve(negf_workspace* w, DBuf& buf, size_t bytes) {
+    const size_t at = (w->arena_off + 255) & ~size_t(255);
+    const size_t want = std::max<size_t>(bytes, 256);
+    if (at > w->arena_cap || want > w->arena_cap - at)
+        return fail(NEGF_EINVAL,
+                    "problem needs more than the %zu bytes of the static scratch area (%zu bytes placed, %zu more "
+                    "requested)",
+                    w->arena_cap, at, want);
+    buf.p = w->arena + at;
+    buf.cap = want;
+    w->arena_off = at + want;
+    return NEGF_OK;
+}
+
 negf_status grow(negf_workspace* w, DBuf& buf, size_t bytes) {
+    if (w->arena) return carve(w, buf, bytes);
     if (bytes <= buf.cap && buf.p) return NEGF_OK;
     if (w->capturing) return fail(NEGF_EINVAL, "graph capture needs a workspace sized by an eager solve");
     if (buf.p) {
@@ -214,6 +230,14 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     HIPCHK(hipSetDevice(w->dev_id));
     // a solve on another stream starts after the previous one (shared arrays)
     if (!w->capturing) HIPCHK(hipStreamWaitEvent(s, w->done, 0));
+    if (w->arena) {   // every buffer is placed afresh in the fixed area
+        DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,   &w->iters, &w->status,
+                        &w->coef_c, &w->coef_r,   &w->T,       &w->gr,      &w->ad,    &w->part,
+                        &w->store_f, &w->store_b, &w->scratch, &w->flags};
+        for (DBuf* b : bufs) *b = DBuf{};
+        w->arena_off = 0;
+        w->last_tables.clear();
+    }
     // ---- per-job array layout
     std::vector<JobPlan> plan(n_jobs);
     size_t nodes = 0, sig = 0, gr64 = 0, gr32 = 0, ad64 = 0, ad32 = 0, part = 0;
@@ -256,6 +280,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     TRY(grow(w, w->flags, (size_t)n_jobs * 2 * 4));
     if (n_jobs > w->cap_flags) {
         if (w->capturing) return fail(NEGF_EINVAL, "graph capture needs a workspace sized by an eager solve");
+        if (w->arena) return fail(NEGF_EINVAL, "allocation-free solve: more jobs than status slots");
         TRY(wait_prev(w));
         if (w->h_flags) (void)hipHostFree(w->h_flags);
         w->h_flags = nullptr;
@@ -393,7 +418,25 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     };
 
     size_t scratch_need = 16, store_need = 0;
-    const size_t store_cap = w->store_cap ? w->store_cap : kDefaultStoreCap;
+    std::vector<int> dec_grid_cap(groups.size(), 0);   // dense one-ring decimation: workgroups its state is sized for
+    size_t store_cap = w->store_cap ? w->store_cap : kDefaultStoreCap;
+    // Arena mode: what is left after the per-node arrays, less a reserve for the
+    // decimation state, the tables and the counters, is split between the two
+    // recursion stores; a dense one-ring decimation runs on fewer workgroups so
+    // that its state fits the reserve.
+    size_t dec_budget = 0;
+    if (w->arena) {
+        size_t ne_all = 0;
+        for (int i = 0; i < n_jobs; ++i) ne_all += (size_t)plan[i].ne;
+        dec_budget = (size_t)16 << 20;
+        const size_t tab_bound = (size_t)n_jobs * (sizeof(negf::JobDesc) + sizeof(negf::RedJob)) +
+                                 (3 * ne_all + 16 * (size_t)n_jobs + 64) * (sizeof(negf::Span) + 2 * sizeof(int)) +
+                                 16 * 256;
+        const size_t used = (w->arena_off + 255) & ~size_t(255);
+        const size_t reserve = dec_budget + tab_bound;
+        const size_t left = w->arena_cap > used + reserve ? w->arena_cap - used - reserve : 0;
+        store_cap = (left / 2) & ~size_t(255);
+    }
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
         Group& g = groups[gi];
         const int B = g.L->B, G = g.L->groups;
@@ -423,8 +466,11 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                 const int kind = P == 1 ? negf::KIND_DECIMATE : negf::KIND_DECIMATE2;
                 const int Gd = P == 1 ? G : 64 / (2 * B);
                 if (P == 1 && (!sp[0][0].empty() || !sp[0][1].empty() || !sp[0][2].empty())) {
-                    const int gdec = persistent_grid(w, g.L->func[kind], 0, 1LL << 40);
-                    scratch_need = std::max(scratch_need, (size_t)gdec * G * 4 * B * B * 16);
+                    int gdec = persistent_grid(w, g.L->func[kind], 0, 1LL << 40);
+                    const size_t per_wg = (size_t)G * 4 * B * B * 16;
+                    if (w->arena) gdec = (int)std::max<size_t>(1, std::min<size_t>(gdec, dec_budget / per_wg));
+                    dec_grid_cap[gi] = gdec;
+                    scratch_need = std::max(scratch_need, (size_t)gdec * per_wg);
                 }
                 for (int m = 0; m < 3; ++m)
                     TRY(add_launch(kind, KT_DECIMATE, gi, sp[P - 1][m], m == 0 ? 2 : 1, m == 2 ? 1 : 0, Gd, false,
@@ -445,9 +491,15 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                 const size_t per = (size_t)jd[j].N * B * B;
                 const long long fit = (long long)((store_cap / cb - used) / per);
                 if (fit <= 0) {
-                    if (used == 0)
+                    if (used == 0) {
+                        if (w->arena)
+                            return fail(NEGF_EINVAL,
+                                        "the static scratch area (%zu bytes) cannot hold one node's recursion "
+                                        "stores (2 x %zu bytes) next to the per-node arrays",
+                                        w->arena_cap, per * cb);
                         return fail(NEGF_ENOMEM, "one node's recursion store (%zu bytes) exceeds the store cap",
                                     per * cb);
+                    }
                     break;
                 }
                 const int take = (int)std::min<long long>(fit, plan[j].ne - e_at);
@@ -529,7 +581,8 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         S.scratch = static_cast<cx<double>*>(w->scratch.p);
         S.tol = g.tol;
         S.maxit = g.maxit;
-        const int grid = persistent_grid(w, g.L->func[L.kind], L.dyn, L.units);
+        int grid = persistent_grid(w, g.L->func[L.kind], L.dyn, L.units);
+        if (L.kind == negf::KIND_DECIMATE && dec_grid_cap[L.group] > 0) grid = std::min(grid, dec_grid_cap[L.group]);
         ev_begin(w, s, &ev);
         g.L->launch[L.kind](S, grid, L.dyn, s);
         ev_end(w, L.kt, s, ev);

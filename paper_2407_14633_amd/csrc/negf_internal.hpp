@@ -85,6 +85,10 @@ struct negf_workspace {
     int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
     bool circ_decimation = true;   // ring-circulant leads decimated in the ring Fourier basis
     bool capturing = false;   // enqueue is being recorded into a graph
+    // Arena mode (allocation-free solves): every buffer is carved from [arena,
+    // arena + arena_cap) at each enqueue instead of being grown with hipMalloc.
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_off = 0;
 };
 
 struct negf_device {

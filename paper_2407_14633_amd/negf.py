@@ -33,6 +33,7 @@ EXPORTED = [
     "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy", "negf_server_create", "negf_server_submit",
     "negf_server_poll", "negf_server_stats", "negf_server_destroy", "negf_modes_create",
     "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy", "negf_semi_adaptive_grid",
+    "negf_solve_dev_static", "negf_static_scratch_bytes",
 ]
 
 
@@ -118,6 +119,10 @@ def load(path: str = LIB_PATH):
     lib.negf_solve_ex.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, C.POINTER(negf_outputs)]
     lib.negf_solve_dev.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
     lib.negf_sync.argtypes = [vp]
+    lib.negf_solve_dev_static.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
+    lib.negf_solve_dev_static.restype = C.c_int
+    lib.negf_static_scratch_bytes.argtypes = []
+    lib.negf_static_scratch_bytes.restype = sz
     lib.negf_lead_self_energy.argtypes = [vp, i, i, vp, vp, vp]
     lib.negf_set_profiling.argtypes = [vp, i]
     lib.negf_kernel_times.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(d), C.POINTER(i), C.POINTER(i)]
@@ -297,6 +302,15 @@ class NegfDevice:
         _check(load().negf_solve_dev(self.h, C.byref(b), nc, _tp(zc), _tp(wc), nr, _tp(Er), _tp(wr), _tp(charge),
                                      _tp(T), _tp(current), s))
 
+    def solve_dev_static(self, bias: Bias, zc, wc, Er, wr, charge, T=None, current=None, stream=None):
+        """solve_dev with every work buffer in the library's fixed device area (no allocation)."""
+        b = negf_bias(bias.mu_L, bias.mu_R, bias.kT_L, bias.kT_R)
+        s = _stream_handle(stream)
+        nc = 0 if zc is None else int(zc.shape[0])
+        nr = 0 if Er is None else int(Er.shape[0])
+        _check(load().negf_solve_dev_static(self.h, C.byref(b), nc, _tp(zc), _tp(wc), nr, _tp(Er), _tp(wr),
+                                            _tp(charge), _tp(T), _tp(current), s))
+
     def sync(self):
         _check(load().negf_sync(self.h))
 
@@ -322,6 +336,11 @@ class NegfDevice:
         _check(load().negf_semi_adaptive_grid(self.h, C.byref(bb), E_l1, E_l2, a, b, _ptr(dens), _ptr(E), _ptr(w),
                                               cap, C.byref(n), _ptr(lim)))
         return E[:n.value].copy(), w[:n.value].copy(), tuple(lim)
+
+
+def static_scratch_bytes() -> int:
+    """Size of the fixed device area used by NegfDevice.solve_dev_static."""
+    return int(load().negf_static_scratch_bytes())
 
 
 def _kernel_times(fn, h) -> dict:
