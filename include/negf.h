@@ -45,7 +45,8 @@ typedef enum {
     NEGF_EINVAL = -1,     /* bad size, NULL pointer, unsupported ring size  */
     NEGF_ENOMEM = -2,     /* device memory allocation failed               */
     NEGF_ENOCONV = -3,    /* decimation did not converge in decim_max_iter */
-    NEGF_ESINGULAR = -4,  /* non-finite pivot or output                    */
+    NEGF_ESINGULAR = -4,  /* non-finite or impossible output (negative
+                             spectral density, T_LR outside [0, b])      */
     NEGF_EHIP = -5,       /* HIP runtime error                             */
     NEGF_PENDING = 1      /* negf_server_poll: the request has not finished */
 } negf_status;
@@ -71,9 +72,19 @@ typedef struct {
 } negf_lead;
 
 typedef struct {
-    int precision;            /* NEGF_FP64, or NEGF_FP32_BULK: recursions, inversions
-                                 and block products in complex FP32 with FP32
-                                 accumulation; decimation and the energy sums FP64  */
+    int precision;            /* NEGF_FP64, or NEGF_FP32_BULK: the ring recursions of
+                                 Algorithm 2 (block inversions, coupling products,
+                                 recursion stores) and the contour diagonals in complex
+                                 FP32 with FP32 accumulation; decimation, the lead-column
+                                 propagation of Algorithm 1 and the energy sums FP64.
+                                 A real-axis node whose FP32 result fails the output
+                                 checks (negative spectral density, T_LR outside
+                                 [0, b]) or whose lead column is large (max |G_{n,0}|,
+                                 |G_{n,N-1}| times (|z| + max row sum of |H|) above 16:
+                                 M is near-singular, as at a bound state) is recomputed
+                                 in FP64 within the same solve; negf_fp64_nodes counts
+                                 them.  ESINGULAR if they do not fit the recursion
+                                 store next to the other nodes.                      */
     double eta;               /* i*eta added to real-axis nodes (device and leads)   */
     double decim_tol;         /* stop when max |alpha_ij|, |beta_ij| < decim_tol (eV) */
     int decim_max_iter;       /* NEGF_ENOCONV beyond this many doubling steps        */
@@ -92,6 +103,8 @@ typedef struct {
     double   *al_diag;      /* [n_r][N*b]  diag A_L at the real-axis nodes        */
     double   *ar_diag;      /* [n_r][N*b]  diag A_R at the real-axis nodes        */
     int      *decim_iters;  /* [n_c+n_r][2] doubling steps taken, left and right  */
+    double   *T_rl;         /* [n_r]    T_RL = Tr[Gamma_R G_{N-1,0} Gamma_L G_{N-1,0}^H]
+                               (Eq. 5 with p = R, q = L; equals T_LR up to O(eta))  */
 } negf_outputs;
 
 /* Fills *opt with eta=1e-6, decim_tol=1e-12, decim_max_iter=64, g_s=2, FP64. */
@@ -186,6 +199,15 @@ negf_status negf_lead_self_energy(negf_device *d, int lead, int n, const negf_c6
 negf_status negf_set_profiling(negf_device *d, int enable);
 negf_status negf_kernel_times(negf_device *d, const char **names, double *ms, int *calls, int *count);
 
+/* FP32-bulk form: real-axis nodes of the last finished solve of d (negf_solve*,
+ * after negf_sync for negf_solve_dev*) that were recomputed in FP64. */
+negf_status negf_fp64_nodes(negf_device *d, int *count);
+
+/* FP32-bulk real-axis nodes recomputed in FP64: 0 (default) the nodes the output
+ * checks mark, 1 every real-axis node (the result then equals the FP64 solve's on
+ * those nodes, bit for bit), 2 none (the plain FP32 result, for measurements). */
+negf_status negf_set_fp64_recompute(negf_device *d, int policy);
+
 /* Device memory held by the handle and its private workspace (bytes). */
 size_t negf_device_bytes(const negf_device *d);
 
@@ -251,6 +273,9 @@ negf_status negf_batch_solve(negf_workspace *w, int n_jobs, const negf_job *jobs
  * (failed_job, if not NULL, receives the index of a failed job or -1). */
 negf_status negf_batch_solve_dev(negf_workspace *w, int n_jobs, const negf_job *jobs, void *hip_stream);
 negf_status negf_batch_sync(negf_workspace *w, int *failed_job);
+/* counts[j] = real-axis nodes of job j recomputed in FP64 in the last finished
+ * batch solve (FP32-bulk jobs; 0 for FP64 jobs). */
+negf_status negf_workspace_fp64_nodes(negf_workspace *w, int n_jobs, int *counts);
 
 /* ---------------------------------------------------------- schedules ----
  * Knobs of the persistent launches; results are bit-identical for every
@@ -262,6 +287,8 @@ typedef struct {
 } negf_schedule;
 
 negf_status negf_workspace_set_order(negf_workspace *w, int order);
+/* negf_set_fp64_recompute for the FP32-bulk jobs of a workspace's batches. */
+negf_status negf_workspace_set_fp64_recompute(negf_workspace *w, int policy);
 /* Basis of the lead decimation (Section 2.2.2).  1 (default): a lead whose
  * blocks and coupling are all ring-circulant (H[i][j] depends on (j - i) mod b,
  * as for a nanotube ring) is decimated in the ring Fourier basis, b scalar

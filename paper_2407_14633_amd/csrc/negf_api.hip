@@ -232,15 +232,15 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     if (!w->capturing) HIPCHK(hipStreamWaitEvent(s, w->done, 0));
     if (w->arena) {   // every buffer is placed afresh in the fixed area
         DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,   &w->iters, &w->status,
-                        &w->coef_c, &w->coef_r,   &w->T,       &w->gr,      &w->ad,    &w->part,
-                        &w->store_f, &w->store_b, &w->scratch, &w->flags};
+                        &w->coef_c, &w->coef_r,   &w->T,       &w->gr,      &w->ad,    &w->part, &w->Trl, &w->amax,
+                        &w->store_f, &w->store_b, &w->scratch, &w->flags, &w->fp64_spans, &w->fp64_first};
         for (DBuf* b : bufs) *b = DBuf{};
         w->arena_off = 0;
         w->last_tables.clear();
     }
     // ---- per-job array layout
     std::vector<JobPlan> plan(n_jobs);
-    size_t nodes = 0, sig = 0, gr64 = 0, gr32 = 0, ad64 = 0, ad32 = 0, part = 0;
+    size_t nodes = 0, sig = 0, gr64 = 0, gr32 = 0, ad = 0, part = 0;
     int max_ne = 0, max_nb = 0;
     w->last_max_iter.assign(n_jobs, 0);
     for (int i = 0; i < n_jobs; ++i) {
@@ -255,7 +255,6 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         p.o_sigma = sig;
         p.o_part = part;
         size_t& gr = d->opt.precision == NEGF_FP32_BULK ? gr32 : gr64;
-        size_t& ad = d->opt.precision == NEGF_FP32_BULK ? ad32 : ad64;
         p.o_gr = gr;
         p.o_ad = ad;
         gr += (size_t)ncz * Nb;
@@ -274,10 +273,12 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     TRY(grow(w, w->coef_c, nodes * 16));
     TRY(grow(w, w->coef_r, nodes * 4 * 8));
     TRY(grow(w, w->T, nodes * 8));
+    TRY(grow(w, w->Trl, nodes * 8));
+    TRY(grow(w, w->amax, nodes * 2 * 8));
     TRY(grow(w, w->gr, gr64 * 16 + gr32 * 8));   // FP64 jobs first, FP32 jobs behind them
-    TRY(grow(w, w->ad, ad64 * 8 + ad32 * 4));
+    TRY(grow(w, w->ad, ad * 8));                   // A_L, A_R diagonals are FP64 in both forms
     TRY(grow(w, w->part, part * 8));
-    TRY(grow(w, w->flags, (size_t)n_jobs * 2 * 4));
+    TRY(grow(w, w->flags, (size_t)n_jobs * kFlagInts * 4));
     if (n_jobs > w->cap_flags) {
         if (w->capturing) return fail(NEGF_EINVAL, "graph capture needs a workspace sized by an eager solve");
         if (w->arena) return fail(NEGF_EINVAL, "allocation-free solve: more jobs than status slots");
@@ -285,7 +286,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         if (w->h_flags) (void)hipHostFree(w->h_flags);
         w->h_flags = nullptr;
         w->cap_flags = 0;
-        HIPCHK(hipHostMalloc((void**)&w->h_flags, (size_t)n_jobs * 2 * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&w->h_flags, (size_t)n_jobs * kFlagInts * sizeof(int), hipHostMallocDefault));
         w->cap_flags = n_jobs;
     }
     char* gr_base = static_cast<char*>(w->gr.p);
@@ -316,10 +317,15 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         D.sigma = J.sigma_mode ? reinterpret_cast<cx<double>*>(J.sigma_cache)
                                : static_cast<cx<double>*>(w->sigma.p) + p.o_sigma;
         D.gr_diag = f32 ? (void*)(gr_base + gr64 * 16 + p.o_gr * 8) : (void*)(gr_base + p.o_gr * 16);
-        D.a_diag = f32 ? (void*)(ad_base + ad64 * 8 + p.o_ad * 4) : (void*)(ad_base + p.o_ad * 8);
+        D.a_diag = (void*)(ad_base + p.o_ad * 8);
         D.Tout = J.T ? J.T : static_cast<double*>(w->T.p) + p.o_node;
+        D.Trl = static_cast<double*>(w->Trl.p) + p.o_node;
+        D.amax = static_cast<double*>(w->amax.p) + 2 * p.o_node;
         D.iters = static_cast<int*>(w->iters.p) + 2 * p.o_node;
         D.status = static_cast<int*>(w->status.p) + p.o_node;
+        D.n_fp64 = static_cast<int*>(w->flags.p) + kFlagInts * i + 2;
+        D.hnorm = d->hnorm;
+        D.fp64_policy = w->fp64_policy;
         for (int l = 0; l < 2; ++l) {
             D.period[l] = d->lead[l].period;
             D.D[l] = d->lead[l].D;
@@ -358,7 +364,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         R.charge = J.charge;
         R.current = J.current;
         R.status = D.status;
-        R.flags = static_cast<int*>(w->flags.p) + 2 * i;
+        R.flags = static_cast<int*>(w->flags.p) + kFlagInts * i;
     }
 
     // ---- groups: jobs sharing kernels (ring size, precision, decimation limits),
@@ -395,14 +401,18 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         int n_spans, sides, side0;
         long long units;
         size_t dyn;
+        int fp64;        // 1: k_fp64_list over a chunk's column spans; 2: a launch over its node list
+        long long cap;   // fp64 == 1: FP64 store elements the chunk's store holds
     };
+    std::vector<int> nfirsts;       // node prefixes of the column spans of k_fp64_list launches
+    long long fp64_max = 0;         // longest node list of one chunk
     std::vector<negf::Span> spans;
     std::vector<int> firsts;
     std::vector<Launch> launches;
     auto add_launch = [&](int kind, int kt, int gidx, const std::vector<negf::Span>& sp, int sides, int side0,
                           int G, bool items, size_t dyn) -> negf_status {
         if (sp.empty()) return NEGF_OK;
-        Launch L{kind, kt, gidx, spans.size(), firsts.size(), (int)sp.size(), sides, side0, 0, dyn};
+        Launch L{kind, kt, gidx, spans.size(), firsts.size(), (int)sp.size(), sides, side0, 0, dyn, 0, 0};
         long long acc = 0;
         for (const auto& x : sp) {
             firsts.push_back((int)acc);
@@ -430,7 +440,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         for (int i = 0; i < n_jobs; ++i) ne_all += (size_t)plan[i].ne;
         dec_budget = (size_t)16 << 20;
         const size_t tab_bound = (size_t)n_jobs * (sizeof(negf::JobDesc) + sizeof(negf::RedJob)) +
-                                 (3 * ne_all + 16 * (size_t)n_jobs + 64) * (sizeof(negf::Span) + 2 * sizeof(int)) +
+                                 (5 * ne_all + 16 * (size_t)n_jobs + 64) * (sizeof(negf::Span) + 2 * sizeof(int)) +
                                  16 * 256;
         const size_t used = (w->arena_off + 255) & ~size_t(255);
         const size_t reserve = dec_budget + tab_bound;
@@ -440,7 +450,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
         Group& g = groups[gi];
         const int B = g.L->B, G = g.L->groups;
-        const size_t cb = g.f32 ? 8 : 16;
+        const size_t cb = g.f32 ? 8 : 16;   // bytes per store element
+        // bytes of store reserved per element: with every real node recomputed in
+        // FP64 the FP32 chunk's store must hold all of them in FP64
+        const size_t cbs = g.f32 && w->fp64_policy == 1 ? 16 : cb;
         // a1: decimation at every node.  One-ring and two-ring principal layers
         // have their own kernels; a job whose leads share the layer size runs
         // both leads in one span (sides 2), otherwise each lead in its own launch.
@@ -479,8 +492,11 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         }
         if (decimation_only) continue;
         // a3-a5: chunks of nodes whose recursion store fits the cap
-        size_t dyn = 0;
-        for (int j : g.ids) dyn = std::max(dyn, (size_t)jd[j].n_uniq * B * jd[j].K * (cb + 1));
+        size_t dyn = 0, dyn64 = 0;
+        for (int j : g.ids) {
+            dyn = std::max(dyn, (size_t)jd[j].n_uniq * B * jd[j].K * (cb + 1));
+            dyn64 = std::max(dyn64, (size_t)jd[j].n_uniq * B * jd[j].K * 17);
+        }
         size_t ji = 0;
         int e_at = 0;
         while (ji < g.ids.size()) {
@@ -489,7 +505,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
             while (ji < g.ids.size()) {
                 const int j = g.ids[ji];
                 const size_t per = (size_t)jd[j].N * B * B;
-                const long long fit = (long long)((store_cap / cb - used) / per);
+                const long long fit = (long long)((store_cap / cbs - used) / per);
                 if (fit <= 0) {
                     if (used == 0) {
                         if (w->arena)
@@ -516,11 +532,28 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                     e_at = 0;
                 }
             }
-            store_need = std::max(store_need, used * cb);
+            store_need = std::max(store_need, used * cbs);
             TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, rec, 2, 0, G, false, dyn));
             TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, G, true, 0));
             TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, G, false,
                            0));
+            if (g.f32 && !col.empty()) {
+                // FP32-bulk: the real-axis nodes whose FP32 results the lead columns
+                // marked are recomputed in FP64 in the chunk's (now free) store
+                long long nreal = 0;
+                Launch LL{negf::KIND_COUNT, KT_COLUMN, gi, spans.size() - col.size(), nfirsts.size(),
+                          (int)col.size(), 1, 0, 0, 0, 1, (long long)(used * cbs / 16)};
+                for (const auto& x : col) {
+                    nfirsts.push_back((int)nreal);
+                    nreal += x.cnt;
+                }
+                nfirsts.push_back((int)nreal);
+                LL.units = nreal;
+                launches.push_back(LL);
+                fp64_max = std::max(fp64_max, nreal);
+                launches.push_back(Launch{negf::KIND_RECUR64, KT_RECUR, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, dyn64, 2, 0});
+                launches.push_back(Launch{negf::KIND_COLUMN64, KT_COLUMN, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0});
+            }
         }
     }
     TRY(grow(w, w->scratch, scratch_need));
@@ -530,6 +563,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     }
     const size_t n_counters = std::max<size_t>(1, launches.size());
     TRY(grow(w, w->counters, n_counters * 4));
+    if (fp64_max) {
+        TRY(grow(w, w->fp64_spans, (size_t)fp64_max * sizeof(negf::Span)));
+        TRY(grow(w, w->fp64_first, (size_t)(fp64_max + 1) * sizeof(int)));
+    }
 
     // ---- tables: one image [JobDesc][RedJob][Span][first], uploaded only when it
     // differs from the last one (repeated solves of the same jobs upload nothing)
@@ -544,6 +581,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     const size_t o_rj = put(rj.data(), rj.size() * sizeof(negf::RedJob));
     const size_t o_sp = put(spans.data(), spans.size() * sizeof(negf::Span));
     const size_t o_fi = put(firsts.data(), firsts.size() * sizeof(int));
+    const size_t o_nf = put(nfirsts.data(), nfirsts.size() * sizeof(int));
     if (img != w->last_tables || !w->tables.p) {
         if (w->capturing) return fail(NEGF_EINVAL, "graph capture: job tables differ from the eager solve");
         TRY(grow(w, w->tables, img.size()));
@@ -556,6 +594,9 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     const negf::RedJob* d_red = reinterpret_cast<const negf::RedJob*>(tab + o_rj);
     const negf::Span* d_spans = reinterpret_cast<const negf::Span*>(tab + o_sp);
     const int* d_first = reinterpret_cast<const int*>(tab + o_fi);
+    const int* d_nfirst = reinterpret_cast<const int*>(tab + o_nf);
+    negf::Span* d_fp64_spans = static_cast<negf::Span*>(w->fp64_spans.p);
+    int* d_fp64_first = static_cast<int*>(w->fp64_first.p);
 
     hipEvent_t ev;
     ev_begin(w, s, &ev);
@@ -568,10 +609,16 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     for (size_t li = 0; li < launches.size(); ++li) {
         const Launch& L = launches[li];
         const Group& g = groups[L.group];
+        if (L.fp64 == 1) {
+            hipLaunchKernelGGL(negf::k_fp64_list, dim3(1), dim3(1024), 0, s, d_jobs, d_red, d_spans + L.span_at,
+                               d_nfirst + L.first_at, L.n_spans, g.L->B, L.cap, d_fp64_spans, d_fp64_first,
+                               (int)L.units);
+            continue;
+        }
         negf::Sched S{};
         S.jobs = d_jobs;
-        S.spans = d_spans + L.span_at;
-        S.first = d_first + L.first_at;
+        S.spans = L.fp64 ? d_fp64_spans : d_spans + L.span_at;
+        S.first = L.fp64 ? d_fp64_first : d_first + L.first_at;
         S.n_spans = L.n_spans;
         S.sides = L.sides;
         S.side0 = L.side0;
@@ -595,7 +642,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         for (int i = 0; i < n_jobs; ++i) {
             const dim3 rgrid((unsigned)((plan[i].d->N * plan[i].d->b + 255) / 256), negf::RED_SEGS, 1);
             if (plan[i].d->opt.precision == NEGF_FP32_BULK)
-                hipLaunchKernelGGL((negf::k_reduce_part<float, float>), rgrid, dim3(256), 0, s, d_red + i);
+                hipLaunchKernelGGL((negf::k_reduce_part<float, double>), rgrid, dim3(256), 0, s, d_red + i);
             else
                 hipLaunchKernelGGL((negf::k_reduce_part<double, double>), rgrid, dim3(256), 0, s, d_red + i);
         }
@@ -603,7 +650,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         hipLaunchKernelGGL(negf::k_current, dim3(n_jobs), dim3(64), 0, s, d_red);
     }
     ev_end(w, KT_REDUCE, s, ev);
-    HIPCHK(hipMemcpyAsync(w->h_flags, w->flags.p, (size_t)n_jobs * 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(w->h_flags, w->flags.p, (size_t)n_jobs * kFlagInts * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipGetLastError());
     if (!w->capturing) HIPCHK(hipEventRecord(w->done, s));
     w->last_n_jobs = n_jobs;
@@ -616,14 +663,25 @@ negf_status finish(negf_workspace* w, int* failed_job) {
     ev_collect(w);
     const int n = w->last_n_jobs;
     w->last_n_jobs = 0;
+    w->last_fp64.assign(n, 0);
+    for (int j = 0; j < n; ++j) w->last_fp64[j] = w->h_flags[kFlagInts * j + 2];
     for (int j = 0; j < n; ++j) {
-        const int fl = w->h_flags[2 * j];
+        const int fl = w->h_flags[kFlagInts * j];
         if (!fl) continue;
         if (failed_job) *failed_job = j;
-        if (fl & 1)
+        const int node = w->h_flags[kFlagInts * j + 1];
+        if (fl & negf::ST_NOCONV)
             return fail(NEGF_ENOCONV, "job %d: lead decimation did not converge in %d steps (first node %d)", j,
-                        w->last_max_iter[j], w->h_flags[2 * j + 1]);
-        return fail(NEGF_ESINGULAR, "job %d: non-finite charge or current (singular block or overflow)", j);
+                        w->last_max_iter[j], node);
+        if (fl & negf::ST_NOROOM)
+            return fail(NEGF_ESINGULAR,
+                        "job %d: FP32-bulk: more real-axis nodes need FP64 recomputation than the recursion store "
+                        "holds (first node %d); solve this job in FP64",
+                        j, node);
+        return fail(NEGF_ESINGULAR,
+                    "job %d: non-finite or impossible output at node %d (negative spectral density, T outside [0, "
+                    "b], or a non-finite charge or current)",
+                    j, node);
     }
     return NEGF_OK;
 }
@@ -646,14 +704,14 @@ negf_status ws_create(negf_workspace** out, size_t store_bytes) {
         delete w;
         return fail(NEGF_EHIP, "event creation failed");
     }
-    if (hipHostMalloc((void**)&w->h_flags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&w->h_flags, kFlagInts * sizeof(int), hipHostMallocDefault) != hipSuccess) {
         (void)hipEventDestroy(w->done);
         (void)hipStreamDestroy(w->own_stream);
         delete w;
         return fail(NEGF_ENOMEM, "pinned flag buffer");
     }
     w->cap_flags = 1;
-    w->h_flags[0] = w->h_flags[1] = 0;
+    for (int k = 0; k < kFlagInts; ++k) w->h_flags[k] = 0;
     *out = w;
     return NEGF_OK;
 }
@@ -667,8 +725,8 @@ void ws_destroy(negf_workspace* w) {
         (void)hipEventDestroy(e.b);
     }
     DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,  &w->iters,      &w->status,
-                    &w->coef_c, &w->coef_r,   &w->T,       &w->gr,     &w->ad,         &w->part,
-                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc,
+                    &w->coef_c, &w->coef_r,   &w->T,       &w->gr,     &w->ad,         &w->part, &w->Trl, &w->amax,
+                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc, &w->fp64_spans, &w->fp64_first,
                     &w->in_Er,  &w->in_wr,    &w->out_charge, &w->out_T, &w->out_cur};
     for (DBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -754,18 +812,14 @@ negf_status solve_host(negf_workspace* w, int n_jobs, const negf_job* jobs, cons
         }
         if ((outs->al_diag || outs->ar_diag) && j.n_r) {
             std::vector<double> ad((size_t)j.n_r * 2 * Nb);
-            if (f32) {
-                std::vector<float> tmp(ad.size());
-                HIPCHK(hipMemcpy(tmp.data(), w->ad.p, tmp.size() * 4, hipMemcpyDeviceToHost));
-                for (size_t i = 0; i < ad.size(); ++i) ad[i] = tmp[i];
-            } else {
-                HIPCHK(hipMemcpy(ad.data(), w->ad.p, ad.size() * 8, hipMemcpyDeviceToHost));
-            }
+            HIPCHK(hipMemcpy(ad.data(), w->ad.p, ad.size() * 8, hipMemcpyDeviceToHost));
             for (int q = 0; q < j.n_r; ++q) {
                 if (outs->al_diag) memcpy(outs->al_diag + (size_t)q * Nb, ad.data() + ((size_t)q * 2 + 0) * Nb, Nb * 8);
                 if (outs->ar_diag) memcpy(outs->ar_diag + (size_t)q * Nb, ad.data() + ((size_t)q * 2 + 1) * Nb, Nb * 8);
             }
         }
+        if (outs->T_rl && j.n_r)
+            HIPCHK(hipMemcpy(outs->T_rl, w->Trl.p, (size_t)j.n_r * 8, hipMemcpyDeviceToHost));
         if (outs->decim_iters)
             HIPCHK(hipMemcpy(outs->decim_iters, w->iters.p, (size_t)(j.n_c + j.n_r) * 2 * 4, hipMemcpyDeviceToHost));
     }
@@ -895,6 +949,21 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
     negf_status s;
     if ((s = ws_create(&d->ws, o.workspace_bytes ? o.workspace_bytes / 2 : 0)) != NEGF_OK) return bail(s);
 
+    // max row sum of |H| over the device rows (on-site block, coupling to the next
+    // ring and from the previous one): the scale of M in the FP32-bulk checks
+    for (int j = 0; j < n_rings; ++j)
+        for (int i = 0; i < b; ++i) {
+            double rs = 0.0;
+            for (int k = 0; k < b; ++k) {
+                rs += std::hypot(h_diag[(size_t)j * b2 + (size_t)i * b + k].re, h_diag[(size_t)j * b2 + (size_t)i * b + k].im);
+                if (j + 1 < n_rings)
+                    rs += std::hypot(h_up[(size_t)j * b2 + (size_t)i * b + k].re, h_up[(size_t)j * b2 + (size_t)i * b + k].im);
+                if (j > 0)   // (H_{j-1,j})^H row i = conj of column i of h_up[j-1]
+                    rs += std::hypot(h_up[(size_t)(j - 1) * b2 + (size_t)k * b + i].re,
+                                     h_up[(size_t)(j - 1) * b2 + (size_t)k * b + i].im);
+            }
+            d->hnorm = std::max(d->hnorm, rs);
+        }
     d->hdiag_zero = true;
     for (size_t i = 0; i < (size_t)n_rings * b2; ++i)
         if (h_diag[i].re != 0.0 || h_diag[i].im != 0.0) {
@@ -1118,6 +1187,18 @@ negf_status negf_kernel_times(negf_device* d, const char** names, double* ms, in
     return negf_workspace_kernel_times(d->ws, names, ms, calls, count);
 }
 
+negf_status negf_fp64_nodes(negf_device* d, int* count) {
+    if (!d || !count) return fail(NEGF_EINVAL, "NULL argument");
+    *count = d->ws->last_fp64.empty() ? 0 : d->ws->last_fp64[0];
+    return NEGF_OK;
+}
+
+negf_status negf_workspace_fp64_nodes(negf_workspace* w, int n_jobs, int* counts) {
+    if (!w || !counts || n_jobs < 0) return fail(NEGF_EINVAL, "bad argument");
+    for (int j = 0; j < n_jobs; ++j) counts[j] = j < (int)w->last_fp64.size() ? w->last_fp64[j] : 0;
+    return NEGF_OK;
+}
+
 size_t negf_device_bytes(const negf_device* d) { return d ? d->bytes + (d->ws ? d->ws->bytes : 0) : 0; }
 
 void negf_destroy(negf_device* d) {
@@ -1166,6 +1247,18 @@ negf_status negf_batch_sync(negf_workspace* w, int* failed_job) {
 negf_status negf_batch_solve(negf_workspace* w, int n_jobs, const negf_job* jobs) {
     TRY(check_batch(w, n_jobs, jobs, true));
     return solve_host(w, n_jobs, jobs, nullptr);
+}
+
+negf_status negf_workspace_set_fp64_recompute(negf_workspace* w, int policy) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    if (policy < 0 || policy > 2) return fail(NEGF_EINVAL, "policy must be 0, 1 or 2");
+    w->fp64_policy = policy;
+    return NEGF_OK;
+}
+
+negf_status negf_set_fp64_recompute(negf_device* d, int policy) {
+    if (!d) return fail(NEGF_EINVAL, "device handle is NULL");
+    return negf_workspace_set_fp64_recompute(d->ws, policy);
 }
 
 negf_status negf_workspace_set_order(negf_workspace* w, int order) {

@@ -33,6 +33,10 @@ const negf::Launchers* launchers_for(int b);
 bool finite_c(const negf_c64* p, size_t n);
 
 enum { KT_DECIMATE = 0, KT_RECUR, KT_CDIAG, KT_COLUMN, KT_REDUCE, KT_COUNT };
+
+// Device flag slots per job: status bits of any node, first bad node, nodes
+// recomputed in FP64 (FP32-bulk form), unused.
+constexpr int kFlagInts = 4;
 extern const char* const kKernelNames[KT_COUNT];
 
 struct LeadDev {
@@ -59,19 +63,21 @@ struct DBuf {
 using negf_host::DBuf;
 using negf_host::LeadDev;
 using negf_host::KT_COUNT;
+using negf_host::kFlagInts;
 
 struct negf_workspace {
     int dev_id = 0;
     size_t store_cap = 0;     // bytes per recursion store direction; 0 = default
     int cus = 0;
     DBuf tables, counters, z, sigma, iters, status, coef_c, coef_r, T, gr, ad, part, store_f, store_b, scratch,
-        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur;
+        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur, fp64_spans, fp64_first, Trl, amax;
     std::vector<char> last_tables;   // host image of `tables` (re-uploaded only when it changes)
     hipEvent_t done = nullptr;       // recorded after each enqueued solve
     int* h_flags = nullptr;   // pinned [2 * cap_flags]
     int cap_flags = 0;
     int last_n_jobs = 0;
     std::vector<int> last_max_iter;
+    std::vector<int> last_fp64;      // per job of the last finished solve: nodes recomputed in FP64
     hipStream_t own_stream = nullptr;
     // profiling
     bool prof = false;
@@ -84,6 +90,7 @@ struct negf_workspace {
     int grid_scale = 1;       // persistent workgroups per (resident workgroups x CU)
     int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
     bool circ_decimation = true;   // ring-circulant leads decimated in the ring Fourier basis
+    int fp64_policy = 0;      // FP32-bulk real nodes recomputed in FP64: 0 marked ones, 1 all, 2 none
     bool capturing = false;   // enqueue is being recorded into a graph
     // Arena mode (allocation-free solves): every buffer is carved from [arena,
     // arena + arena_cap) at each enqueue instead of being grown with hipMalloc.
@@ -98,6 +105,7 @@ struct negf_device {
     const negf::Launchers* L = nullptr;
     int K = 1, n_uniq = 1;
     bool hdiag_zero = true;
+    double hnorm = 0.0;             // max row sum of |H| (on-site blocks and both couplings)
     double* d_U = nullptr;
     cx<double>* d_hdiag = nullptr;
     int* d_ell_map = nullptr;

@@ -425,6 +425,11 @@ __device__ __forceinline__ void stage_row(const T (&xr)[B], const T (&xi)[B], cx
 }
 
 // ------------------------------------------------------------- arguments
+// Per-node status bits: decimation did not converge; non-finite or impossible
+// output (negative spectral density, T outside [0, B]); FP64 recomputation needed
+// but no room left in the chunk's store; FP32 result marked for FP64 recomputation.
+enum { ST_NOCONV = 1, ST_BAD = 2, ST_NOROOM = 4, ST_FP64 = 256 };
+
 struct JobDesc {
     int N, n_c, n_r;          // rings, contour nodes (first n_c), real-axis nodes
     int K, n_uniq;            // ELL width and number of distinct coupling blocks
@@ -439,10 +444,15 @@ struct JobDesc {
     const cx<double>* z;      // [n_e] nodes (real nodes carry i*eta)
     cx<double>* sigma;        // [n_e][2][b][b] lead self-energies (left, right)
     void* gr_diag;            // [n_c][N*b] cx<T>
-    void* a_diag;             // [n_r][2][N*b] T
-    double* Tout;             // [n_r]
+    void* a_diag;             // [n_r][2][N*b] double
+    double* Tout;             // [n_r] T_LR
+    double* Trl;              // [n_r] T_RL (from the left lead column)
+    double* amax;             // [n_r][2] max_i A_l,ii per real node and lead
     int* iters;               // [n_e][2] decimation steps
-    int* status;              // [n_e]    |= 1 when a decimation did not converge
+    int* status;              // [n_e]    ST_* bits: decimation, bad output, FP64 recompute
+    int* n_fp64;              // number of nodes recomputed in FP64 (FP32-bulk form)
+    double hnorm;             // max row sum of |H| over the device (couplings included)
+    int fp64_policy;          // FP32-bulk: 0 recompute the marked real nodes, 1 all, 2 none
     int period[2];            // lead principal-layer sizes
     const cx<double>* D[2];   // [period][b][b] lead on-site blocks incl. lead potential
     const cx<double>* V[2];   // h_up[0]
@@ -815,11 +825,29 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 // backward store, W_{n+1} = -x~_n W_n (the off-diagonal column recursions of Algorithm 1).
 // Each ring's diag(W Gamma W^H) is written; the right chain ends with
 // T_LR = Tr[Gamma_L W_0 Gamma_R W_0^H] (Eq. 5).
-template <typename T, int B>
+//
+// The propagation runs in FP64 whatever the store precision TS: the product
+// chain W_{n+1} = -x~_n W_n is unstable in FP32 where W's columns span many
+// orders of magnitude (real nodes next to a pole of a lead's surface Green's
+// function), even when the recursion stores are exact.
+//
+// Output checks at the end of every chain: the spectral densities diag(W Gamma W^H)
+// must not be negative (Gamma is positive semidefinite) and T_LR must lie in
+// [0, B] (at most B channels through a B-atom ring).  With FP64 stores a
+// violation sets status bit 2 of the node (an error); with FP32 stores it, or a
+// large lead column (max |W_ij| (|z| + ||H||) > NEGF_FP32_WMAX: the whole-device
+// Green's function is then large, i.e. M is near-singular and the FP32
+// recursion has lost digits), marks the node for recomputation in FP64 (bit 8).
+#ifndef NEGF_FP32_WMAX
+#define NEGF_FP32_WMAX 16.0
+#endif
+template <typename TS, int B>
 __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per_eu(NEGF_RGF_WAVES, NEGF_RGF_WAVES))) void k_column(Sched S) {
+    using T = double;
     constexpr int G = 64 / B;
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_gam[G][B * B];
+    __shared__ double s_chk[G][4][B];
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
@@ -848,19 +876,20 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
                 Gm[r * B + j] = cx<T>{T(-(a.im + b.im)), T(a.re - b.re)};
             }
         }
-        const cx<T>* store = reinterpret_cast<const cx<T>*>(lead ? S.store_f : S.store_b) + u.off +
-                             (size_t)(u.i0 + (act ? gi : 0)) * N * B * B;
+        const cx<TS>* store = reinterpret_cast<const cx<TS>*>(lead ? S.store_f : S.store_b) + u.off +
+                              (size_t)(u.i0 + (act ? gi : 0)) * N * B * B;
         T wr[B], wi[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) { wr[j] = T(0); wi[j] = T(0); }
         if (act) {
-            const cx<T>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
+            const cx<TS>* w0 = store + ((size_t)(lead ? 0 : N - 1) * B + r) * B;
 #pragma unroll
-            for (int j = 0; j < B; ++j) { const cx<T> v = gload(w0 + j); wr[j] = v.re; wi[j] = v.im; }
+            for (int j = 0; j < B; ++j) { const cx<TS> v = gload(w0 + j); wr[j] = v.re; wi[j] = v.im; }
         }
         stage_row<T, B>(wr, wi, St, r, act);
         wave_sync();
-        T* aout = reinterpret_cast<T*>(J.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
+        double* aout = reinterpret_cast<double*>(J.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
+        double wmag = 0.0, amin = 0.0, amax = 0.0;   // this row's max |W_rj| and range of A_rr
 
         for (int s = 0; s < N; ++s) {
             const int n = lead ? N - 1 - s : s;
@@ -869,10 +898,12 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int j = 0; j < B; ++j) { pr[j] = T(0); pi[j] = T(0); }
             if (act && s < N - 1) {
-                const cx<T>* p = store + ((size_t)n * B + r) * B;
+                const cx<TS>* p = store + ((size_t)n * B + r) * B;
 #pragma unroll
-                for (int j = 0; j < B; ++j) { const cx<T> v = gload(p + j); pr[j] = -v.re; pi[j] = -v.im; }
+                for (int j = 0; j < B; ++j) { const cx<TS> v = gload(p + j); pr[j] = -T(v.re); pi[j] = -T(v.im); }
             }
+#pragma unroll
+            for (int j = 0; j < B; ++j) wmag = fmax(wmag, fabs(wr[j]) + fabs(wi[j]));
             // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j]).  Gamma does not
             // change along the chain; its offset is made opaque each step so that its
             // B*B reads are not hoisted out of the loop into (spilled) registers.
@@ -883,6 +914,8 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             const T acc = gcirc ? row_quad_circ<T, B>(wr, wi, &s_gam[0][0] + goff)
                                 : row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
             if (act) gstore_s(aout + (size_t)n * B + r, acc);
+            amin = s == 0 ? acc : fmin(amin, acc);
+            amax = s == 0 ? acc : fmax(amax, acc);
             if (s == N - 1) break;
             // W_next[r][:] = -sum_k P[r][k] W[k][:],  P = y~_n (right) or x~_n (left)
             row_mul_pipe<T, B>(pr, pi, St, wr, wi);
@@ -890,36 +923,58 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             stage_row<T, B>(wr, wi, St, r, act);
             wave_sync();
         }
-        if (lead == 1) {
-            // W = G_{0,N-1} (in St and registers), v = W Gamma_R.
-            // T_LR = sum_{r,j'} Gamma_L[j'][r] (W Gamma_R W^H)[r][j']
+        // Transmission from the far end of the chain (Eq. 5): the right chain ends with
+        // W = G_{0,N-1} and gives T_LR = Tr[Gamma_L W Gamma_R W^H]; the left chain ends
+        // with W = G_{N-1,0} and gives T_RL = Tr[Gamma_R W Gamma_L W^H].  Both are formed
+        // as sum_{r,j'} Gamma_o[j'][r] (W Gamma_l W^H)[r][j'] with this lead's Gamma_l in
+        // LDS and the other lead's Gamma_o read from its self-energy.
+        double t = 0.0;
+        {
             T vr[B], vi[B];
             row_mul<T, B>(wr, wi, Gm, vr, vi);
-            double t = 0.0;
             if (act) {
-                const cx<double>* sl = J.sigma + ((size_t)e * 2 + 0) * B * B;
+                const cx<double>* sl = J.sigma + ((size_t)e * 2 + (1 - lead)) * B * B;
                 for (int jp = 0; jp < B; ++jp) {
                     double mr = 0.0, mi = 0.0;   // (W Gamma_R W^H)[r][jp] = sum_j v[j] conj(W[jp][j])
 #pragma unroll
                     for (int j = 0; j < B; ++j) {
                         const cx<T> wv = St[jp * B + j];
-                        mr += (double)vr[j] * (double)wv.re + (double)vi[j] * (double)wv.im;
-                        mi += (double)vi[j] * (double)wv.re - (double)vr[j] * (double)wv.im;
+                        mr += vr[j] * wv.re + vi[j] * wv.im;
+                        mi += vi[j] * wv.re - vr[j] * wv.im;
                     }
                     const cx<double> a = gload(sl + jp * B + r), b = gload(sl + r * B + jp);
-                    const double gre = -(a.im + b.im), gim = a.re - b.re;   // Gamma_L[jp][r]
+                    const double gre = -(a.im + b.im), gim = a.re - b.re;   // Gamma_o[jp][r]
                     t += gre * mr - gim * mi;
                 }
             }
-            // group sum in fixed order through LDS (Gm is free now)
-            wave_sync();
-            double* red = reinterpret_cast<double*>(Gm);
-            if (act) red[r] = t;
-            wave_sync();
-            if (act && r == 0) {
-                double sum = 0.0;
-                for (int q = 0; q < B; ++q) sum += red[q];
-                gstore_s(J.Tout + ir, sum);
+        }
+        // chain-wide sums and extremes in fixed order through LDS
+        wave_sync();
+        if (act) {
+            s_chk[gsafe][0][r] = t;
+            s_chk[gsafe][1][r] = wmag;
+            s_chk[gsafe][2][r] = amin;
+            s_chk[gsafe][3][r] = amax;
+        }
+        wave_sync();
+        if (act && r == 0) {
+            double tsum = 0.0, wm = 0.0, amn = s_chk[gsafe][2][0], amx = s_chk[gsafe][3][0];
+            for (int q = 0; q < B; ++q) {
+                tsum += s_chk[gsafe][0][q];
+                wm = fmax(wm, s_chk[gsafe][1][q]);
+                amn = fmin(amn, s_chk[gsafe][2][q]);
+                amx = fmax(amx, s_chk[gsafe][3][q]);
+            }
+            gstore_s((lead == 1 ? J.Tout : J.Trl) + ir, tsum);
+            gstore_s(J.amax + 2 * ir + lead, amx);
+            const bool bad_T = !(tsum >= -1e-6 && tsum <= B * (1.0 + 1e-6));
+            const bool bad_A = !(amn >= -1e-6 * fabs(amx)) || !(amx < 1e300);
+            if constexpr (sizeof(TS) == 4) {
+                const cx<double> z = gload(J.z + e);
+                const bool big_w = wm * (fabs(z.re) + fabs(z.im) + J.hnorm) > NEGF_FP32_WMAX;
+                if (bad_T || bad_A || big_w) atomicOr(&J.status[e], (int)ST_FP64);
+            } else {
+                if (bad_T || bad_A) atomicOr(&J.status[e], (int)ST_BAD);
             }
         }
         wave_sync();
@@ -1106,7 +1161,7 @@ __device__ __forceinline__ void decimate_chain1(const JobDesc& J, int lead, doub
     if (act) sigma_row<B, B>(J.tau[lead], L0, r, J.sigma + ((size_t)k * 2 + lead) * B * B);
     if (act && r == 0) {
         J.iters[(size_t)k * 2 + lead] = it_done;
-        if (!converged) atomicOr(&J.status[k], 1);
+        if (!converged) atomicOr(&J.status[k], (int)ST_NOCONV);
     }
 }
 
@@ -1284,7 +1339,7 @@ __global__ __launch_bounds__(64) void k_decimate2(Sched S) {
         if (act && top) sigma_row<B, BB>(J.tau[lead], Sg, i, J.sigma + ((size_t)k * 2 + lead) * B * B);
         if (act && q == 0) {
             J.iters[(size_t)k * 2 + lead] = it_done;
-            if (!converged) atomicOr(&J.status[k], 1);
+            if (!converged) atomicOr(&J.status[k], (int)ST_NOCONV);
         }
         wave_sync();
     }
@@ -1403,7 +1458,7 @@ __global__ __launch_bounds__(64) void k_decimate_circ(Sched S) {
             for (int j = 0; j < B; ++j) out[j] = s_sig[gsafe][(q - j + B) % B];
             if (q == 0) {
                 J.iters[(size_t)k * 2 + lead] = it_done;
-                if (!converged) atomicOr(&J.status[k], 1);
+                if (!converged) atomicOr(&J.status[k], (int)ST_NOCONV);
             }
         } else {
             wave_sync();

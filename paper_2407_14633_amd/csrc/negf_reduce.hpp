@@ -27,8 +27,9 @@ struct RedJob {
     double* charge;            // [Nb]
     double* current;           // [1] or null
     double* conductance;       // [1] or null: g_s (e^2/h) sum w T (-dF/dE), Eq. 6
-    const int* status;         // [n_c + n_r] decimation status
-    int* flags;                // [2]: bit 1 no convergence, bit 2 non-finite; first bad node
+    const int* status;         // [n_c + n_r] ST_* bits per node
+    int* flags;                // [4]: ST_NOCONV | ST_BAD | ST_NOROOM of any node; first bad node;
+                               //      nodes recomputed in FP64; unused
 };
 
 __device__ __forceinline__ double fermi_real(double E, double mu, double kT) {
@@ -79,7 +80,7 @@ __global__ void k_nodes(const RedJob* jobs, int* status_all, int status_n) {
     if (blockIdx.y == 0) {
         for (int i = e; i < status_n; i += gridDim.x * blockDim.x) status_all[i] = 0;
     }
-    if (e == 0) { J.flags[0] = 0; J.flags[1] = 0x7fffffff; }
+    if (e == 0) { J.flags[0] = 0; J.flags[1] = 0x7fffffff; J.flags[2] = 0; J.flags[3] = 0; }
 }
 
 __global__ void k_coef(const RedJob* jobs) {
@@ -110,8 +111,9 @@ __global__ void k_coef(const RedJob* jobs) {
         R.coef_r[4 * q + 2] = w * fermi_diff(R.E_r[q], R.mu_L, R.kT_L, R.mu_R, R.kT_R);
         R.coef_r[4 * q + 3] = w / (4.0 * R.kT_L * ch * ch);
     }
-    if (e < R.n_c + R.n_r && R.status[e]) {
-        atomicOr(R.flags, R.status[e]);
+    const int st = e < R.n_c + R.n_r ? (R.status[e] & (ST_NOCONV | ST_BAD | ST_NOROOM)) : 0;
+    if (st) {
+        atomicOr(R.flags, st);
         atomicMin(R.flags + 1, e);
     }
 }
@@ -156,7 +158,7 @@ __global__ void k_reduce_final(const RedJob* jobs) {
     for (int seg = 0; seg < RED_SEGS; ++seg) acc += R.part[(size_t)seg * R.Nb + i];
     const double ch = R.g_s * acc;
     R.charge[i] = ch;
-    if (!isfinite(ch)) atomicOr(R.flags, 2);
+    if (!isfinite(ch)) atomicOr(R.flags, (int)ST_BAD);
 }
 
 // current: one wavefront per job, lane l sums nodes l, l+64, ... then a fixed tree
@@ -184,8 +186,106 @@ __global__ __launch_bounds__(64) void k_current(const RedJob* jobs) {
         const double cur = R.g_s * G0 * red[0][0];
         if (R.current) *R.current = cur;
         if (R.conductance) *R.conductance = R.g_s * G0 * red[1][0];
-        if (!isfinite(cur)) atomicOr(R.flags, 2);
+        if (!isfinite(cur)) atomicOr(R.flags, (int)ST_BAD);
     }
+}
+
+// Charge (electrons per atom) a node may move before its FP32 result is replaced.
+#ifndef NEGF_FP32_QTOL
+#define NEGF_FP32_QTOL 1e-7
+#endif
+
+// FP32-bulk, after the lead columns of one chunk: the real-axis nodes to recompute
+// in FP64.  A node is taken when the lead columns marked it (ST_FP64), or when its
+// two transmissions disagree by more than its weight allows: T_LR comes from the
+// right lead column (forward recursion), T_RL from the left one (backward
+// recursion), and they agree up to O(eta) unless an FP32 recursion lost digits;
+// with r = |T_LR - T_RL| / max(T_LR, T_RL) and the node's largest charge term
+// c = g_s (|w|/pi) (f_L max_i A_L,ii + f_R max_i A_R,ii), the node is taken when
+// c sqrt(r) > NEGF_FP32_QTOL (sqrt(r): the spectral densities were measured to be
+// off by up to ~100 r on the nanotube workloads).  The taken nodes get slots of
+// FP64 recursion store in node order while the slots fit the chunk's store (cap
+// FP64 elements, the FP32 data being dead by then); each becomes a one-node span
+// of the FP64 recursion and column launches that follow (units: two per span,
+// directions or leads).  A taken node that does not fit is marked ST_NOROOM.
+// col[0..n_col) are the chunk's column spans, col_first their node prefix.  One
+// workgroup of 1024 threads; the order is that of the nodes.
+__global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const RedJob* red, const Span* col,
+                                                   const int* col_first, int n_col, int B, long long cap, Span* out,
+                                                   int* out_first, int max_out) {
+    __shared__ long long s_sz[1024];
+    __shared__ int s_ct[1024];
+    __shared__ long long s_base;
+    __shared__ int s_seen, s_emit;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_base = 0;
+        s_seen = 0;
+        s_emit = 0;
+    }
+    __syncthreads();
+    const int total = col_first[n_col];
+    for (int base = 0; base < total; base += 1024) {
+        const int t = base + tid;
+        int job = 0, e = 0, ct = 0;
+        long long sz = 0;
+        if (t < total) {
+            int lo = 0, hi = n_col;   // col_first[lo] <= t < col_first[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (col_first[mid] <= t) lo = mid; else hi = mid;
+            }
+            const Span sp = col[lo];
+            job = sp.job;
+            e = sp.e0 + (t - col_first[lo]);
+            const JobDesc& J = jobs[job];
+            const RedJob& R = red[job];
+            const int ir = e - J.n_c;
+            const double t1 = J.Tout[ir], t2 = J.Trl[ir];
+            const double tmax = fmax(fabs(t1), fabs(t2));
+            const double r = tmax > 0.0 ? fabs(t1 - t2) / tmax : 0.0;
+            const double E = R.E_r[ir];
+            const double c = R.g_s * fabs(R.w_r[ir]) * 0.31830988618379067154 *
+                             (fermi_real(E, R.mu_L, R.kT_L) * J.amax[2 * ir] +
+                              fermi_real(E, R.mu_R, R.kT_R) * J.amax[2 * ir + 1]);
+            const bool recip = !(c * sqrt(r) <= NEGF_FP32_QTOL);
+            const bool mark = J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e] & ST_FP64) || recip));
+            if (mark) {
+                ct = 1;
+                sz = (long long)jobs[job].N * B * B;
+            }
+        }
+        s_sz[tid] = sz;
+        s_ct[tid] = ct;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {   // inclusive scans of sizes and counts
+            const long long a = tid >= d ? s_sz[tid - d] : 0;
+            const int c = tid >= d ? s_ct[tid - d] : 0;
+            __syncthreads();
+            s_sz[tid] += a;
+            s_ct[tid] += c;
+            __syncthreads();
+        }
+        if (ct) {
+            // offsets grow with the node order, so the nodes that fit are a prefix
+            const long long off = s_base + s_sz[tid] - sz;
+            const int idx = s_seen + s_ct[tid] - 1;
+            if (off + sz <= cap && idx < max_out) {
+                out[idx] = Span{job, e, 1, 0, off};
+                atomicAdd(jobs[job].n_fp64, 1);
+                atomicAdd(&s_emit, 1);
+            } else {
+                atomicOr(&jobs[job].status[e], (int)ST_NOROOM);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_base += s_sz[1023];
+            s_seen += s_ct[1023];
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k <= max_out; k += 1024) out_first[k] = 2 * min(k, s_emit);
 }
 
 __global__ void k_fill_int(int* p, int n, int v) {

@@ -273,18 +273,18 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->passes++;
     }
-    // per-request NEGF flags (bit 1: decimation, bit 2: non-finite result)
+    // per-request NEGF flags (ST_NOCONV: decimation; ST_BAD / ST_NOROOM: bad result)
     std::vector<ScJob*> keep;
     for (size_t k = 0; k < S->running.size(); ++k) {
         ScJob* j = S->running[k];
         j->sigma_ready = true;
-        const int fl = S->ws->h_flags[2 * k];
+        const int fl = S->ws->h_flags[kFlagInts * k];
         const int* st = S->h_stat + 4 * j->slot;
         j->passes = st[1];
         j->eps_max = S->h_diag[2 * j->slot];
         j->trace.push_back(j->eps_max);
         if (fl) {
-            finish_job(S, j, (fl & 1) ? NEGF_ENOCONV : NEGF_ESINGULAR);
+            finish_job(S, j, (fl & negf::ST_NOCONV) ? NEGF_ENOCONV : NEGF_ESINGULAR);
         } else if (st[2] == 1) {
             finish_job(S, j, NEGF_OK);
         } else if (st[2] == 2) {

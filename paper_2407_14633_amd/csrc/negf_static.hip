@@ -85,6 +85,7 @@ negf_status negf_solve_dev_static(negf_device* d, const negf_bias* bias, int n_c
     w.grid_scale = own->grid_scale;
     w.order = own->order;
     w.circ_decimation = own->circ_decimation;
+    w.fp64_policy = own->fp64_policy;
     w.arena = area;
     w.arena_cap = kScratchBytes;
     const negf_status st = enqueue(&w, 1, &j, (hipStream_t)hip_stream);

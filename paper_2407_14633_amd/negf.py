@@ -33,7 +33,8 @@ EXPORTED = [
     "negf_graph_launch", "negf_graph_sync", "negf_graph_destroy", "negf_server_create", "negf_server_submit",
     "negf_server_poll", "negf_server_stats", "negf_server_destroy", "negf_modes_create",
     "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy", "negf_semi_adaptive_grid",
-    "negf_solve_dev_static", "negf_static_scratch_bytes",
+    "negf_solve_dev_static", "negf_static_scratch_bytes", "negf_fp64_nodes", "negf_workspace_fp64_nodes",
+    "negf_set_fp64_recompute", "negf_workspace_set_fp64_recompute",
 ]
 
 
@@ -62,7 +63,8 @@ class negf_bias(C.Structure):
 
 class negf_outputs(C.Structure):
     _fields_ = [("charge", C.c_void_p), ("T", C.c_void_p), ("current", C.c_void_p), ("gr_diag", C.c_void_p),
-                ("al_diag", C.c_void_p), ("ar_diag", C.c_void_p), ("decim_iters", C.c_void_p)]
+                ("al_diag", C.c_void_p), ("ar_diag", C.c_void_p), ("decim_iters", C.c_void_p),
+                ("T_rl", C.c_void_p)]
 
 
 class negf_job(C.Structure):
@@ -119,6 +121,14 @@ def load(path: str = LIB_PATH):
     lib.negf_solve_ex.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, C.POINTER(negf_outputs)]
     lib.negf_solve_dev.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
     lib.negf_sync.argtypes = [vp]
+    lib.negf_set_fp64_recompute.argtypes = [vp, i]
+    lib.negf_set_fp64_recompute.restype = C.c_int
+    lib.negf_workspace_set_fp64_recompute.argtypes = [vp, i]
+    lib.negf_workspace_set_fp64_recompute.restype = C.c_int
+    lib.negf_fp64_nodes.argtypes = [vp, C.POINTER(i)]
+    lib.negf_fp64_nodes.restype = C.c_int
+    lib.negf_workspace_fp64_nodes.argtypes = [vp, i, C.POINTER(i)]
+    lib.negf_workspace_fp64_nodes.restype = C.c_int
     lib.negf_solve_dev_static.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
     lib.negf_solve_dev_static.restype = C.c_int
     lib.negf_static_scratch_bytes.argtypes = []
@@ -213,6 +223,8 @@ class SolveResult:
     ar_diag: Optional[np.ndarray] = None
     decim_iters: Optional[np.ndarray] = None
     conductance: Optional[float] = None
+    fp64_nodes: int = 0
+    T_rl: Optional[np.ndarray] = None
 
 
 class NegfDevice:
@@ -272,9 +284,11 @@ class NegfDevice:
         charge = np.zeros(nb)
         T = np.zeros(nr)
         cur = np.zeros(1)
-        out = negf_outputs(_ptr(charge), _ptr(T), _ptr(cur), None, None, None, None)
-        gr = al = ar = it = None
+        out = negf_outputs(_ptr(charge), _ptr(T), _ptr(cur), None, None, None, None, None)
+        gr = al = ar = it = trl = None
         if details:
+            trl = np.zeros(nr)
+            out.T_rl = _ptr(trl)
             gr = np.zeros((nc, nb), np.complex128)
             al = np.zeros((nr, nb))
             ar = np.zeros((nr, nb))
@@ -283,7 +297,7 @@ class NegfDevice:
         b = negf_bias(bias.mu_L, bias.mu_R, bias.kT_L, bias.kT_R)
         _check(load().negf_solve_ex(self.h, C.byref(b), nc, _ptr(zc), _ptr(wc), nr, _ptr(Er), _ptr(wr),
                                     C.byref(out)))
-        return SolveResult(charge, T, float(cur[0]), gr, al, ar, it)
+        return SolveResult(charge, T, float(cur[0]), gr, al, ar, it, fp64_nodes=self.fp64_nodes(), T_rl=trl)
 
     def lead_self_energy(self, lead: int, z: np.ndarray):
         z = _c(np.atleast_1d(z), np.complex128)
@@ -313,6 +327,16 @@ class NegfDevice:
 
     def sync(self):
         _check(load().negf_sync(self.h))
+
+    def set_fp64_recompute(self, policy: int):
+        """FP32-bulk: 0 recompute the marked real nodes in FP64, 1 all of them, 2 none."""
+        _check(load().negf_set_fp64_recompute(self.h, int(policy)))
+
+    def fp64_nodes(self) -> int:
+        """FP32-bulk: real-axis nodes of the last solve that were recomputed in FP64."""
+        n = C.c_int(0)
+        _check(load().negf_fp64_nodes(self.h, C.byref(n)))
+        return int(n.value)
 
     def set_profiling(self, on: bool):
         _check(load().negf_set_profiling(self.h, 1 if on else 0))
@@ -429,6 +453,12 @@ class Workspace:
         arr = _dev_jobs(jobs)
         _check(load().negf_batch_solve_dev(self.h, len(jobs), arr, _stream_handle(stream)))
 
+    def fp64_nodes(self, n_jobs: int) -> list:
+        """Per job of the last batch: real-axis nodes recomputed in FP64 (FP32-bulk jobs)."""
+        a = (C.c_int * max(1, n_jobs))()
+        _check(load().negf_workspace_fp64_nodes(self.h, int(n_jobs), a))
+        return [int(a[k]) for k in range(n_jobs)]
+
     def set_order(self, order: int):
         _check(load().negf_workspace_set_order(self.h, int(order)))
 
@@ -523,11 +553,14 @@ def _stream_handle(stream):
     return C.c_void_p(int(stream))
 
 
-def solve_problem(p: Problem, precision: int = FP64, details: bool = False, **kw) -> SolveResult:
+def solve_problem(p: Problem, precision: int = FP64, details: bool = False, fp64_recompute: int = 0,
+                  **kw) -> SolveResult:
     """Creates a handle for p.device, sets the potential and solves p's grid."""
     with NegfDevice(p.device, precision=precision, eta=p.eta, decim_tol=p.decim_tol,
                     decim_max_iter=p.decim_max_iter, g_s=p.g_s, **kw) as d:
         d.set_potential(p.U, p.U_left, p.U_right)
+        if fp64_recompute:
+            d.set_fp64_recompute(fp64_recompute)
         return d.solve(p.bias, p.grid, details=details)
 
 

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_symbols():
     hdr = open(os.path.join(ROOT, "include", "negf.h")).read()
     hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
-    return sorted(set(re.findall(r"\b(negf_[a-z_]+)\s*\(", hdr)))
+    return sorted(set(re.findall(r"\b(negf_[a-z0-9_]+)\s*\(", hdr)))
 
 
 @pytest.fixture(scope="module")
@@ -187,3 +187,10 @@ def test_modes_and_grid_reject_bad_arguments(lib):
     n = C.c_int()
     assert lib.negf_semi_adaptive_grid(None, None, 0.0, 0.0, 3.0, 1.0, None, None, None, 0, C.byref(n), None) \
         == NG.NEGF_EINVAL
+
+
+def test_fp64_recompute_policy_rejected_without_gpu_work(lib):
+    assert lib.negf_set_fp64_recompute(None, 0) == NG.NEGF_EINVAL
+    assert lib.negf_workspace_set_fp64_recompute(None, 1) == NG.NEGF_EINVAL
+    n = C.c_int(7)
+    assert lib.negf_fp64_nodes(None, C.byref(n)) == NG.NEGF_EINVAL

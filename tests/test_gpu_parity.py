@@ -3,8 +3,8 @@
 FP64 gate: 1e-10 relative on integrated per-atom charge (denominator max_i |charge_i|)
 and on the current; per-energy quantities are compared with a floor (the
 problem's own conditioning near resonances is ~1e-10 per energy).
-FP32-bulk: the current and T(E) are held to 1e-5 and 1e-3; the per-atom charge
-error is measured and reported (see FP32_BULK_BOUND below).
+FP32-bulk: per-atom charge and current are held to 1e-5 relative, T(E) to 1e-3
+with a floor.
 """
 import sys
 
@@ -214,23 +214,22 @@ def test_small_problem_fp64(gpu_lib, small_ref):
     assert np.array_equal(got.decim_iters[:, 0] > 0, np.ones(256, bool))
 
 
-# FP32 recursions and column propagation lose accuracy at near-resonant real-axis
-# nodes (eta = 1e-6): a complex64 emulation of the same algorithm gives the same
-# ~3e-3 charge error on the (8,0) workload.  Zigzag rings carry no intra-ring
-# bond, so a ring block is (z - U) I and is nearly singular wherever a real node
-# lies close to the on-site potential; next to the lead edge-state pole at
-# E = U_lead the FP32 recursion loses every digit (a complex64 emulation agrees).
-# The FP32-bulk charge error is therefore measured and reported against a loose
-# bound on grids that avoid that pole, and only checked finite on the full grid.
-FP32_BULK_BOUND = 5e-2
+# FP32-bulk contract: 1e-5 relative on per-atom charge and on the current against
+# the FP64 oracle.  The (8,0) workload has a bound state (broadened by eta alone)
+# 1.4e-5 eV from the node at -0.4648 eV, where M's condition number is 9e5: no FP32
+# solve keeps a digit there, and the library recomputes such nodes in FP64 (55 of
+# the 256 on this workload, whose in-gap nodes sit near resonances of the well).
+FP32_BULK_BOUND = 1e-5
 
 
-def test_small_problem_fp32_bulk_error_reported(gpu_lib, small_ref):
+def test_small_problem_fp32_bulk(gpu_lib, small_ref):
     p, ref = small_ref
     got = gpu_lib.solve_problem(p, precision=gpu_lib.FP32_BULK)
     e_q = rel(got.charge, ref["charge"])
-    say(f"  fp32-bulk small: charge rel {e_q:.3e}")
-    assert e_q < FP32_BULK_BOUND
+    e_c = abs(got.current - ref["current"]) / abs(ref["current"])
+    say(f"  fp32-bulk small: charge rel {e_q:.3e} current rel {e_c:.3e}, {got.fp64_nodes} nodes in FP64")
+    assert e_q < FP32_BULK_BOUND and e_c < FP32_BULK_BOUND
+    assert 1 <= got.fp64_nodes <= p.grid.n_r // 3   # FP32 still carries most nodes
 
 
 def test_energy_chunking_is_bitwise_invariant(gpu_lib, small_ref):
@@ -326,33 +325,36 @@ def test_device_problem_sampled_reduced_precision(gpu_lib, device_sub, mode):
     got = gpu_lib.solve_problem(ps, precision=getattr(gpu_lib, mode))
     e_q = rel(got.charge, ref["charge"])
     e_c = abs(got.current - ref["current"]) / abs(ref["current"])
-    say(f"  {mode} device: charge rel {e_q:.3e} current rel {e_c:.3e}")
-    assert e_q < FP32_BULK_BOUND and e_c < 1e-5
+    say(f"  {mode} device: charge rel {e_q:.3e} current rel {e_c:.3e}, {got.fp64_nodes} nodes in FP64")
+    assert e_q < FP32_BULK_BOUND and e_c < FP32_BULK_BOUND
 
 
 # ---------------------------- full 512 + 1536 grid vs the stored oracle result ----
-@pytest.fixture(scope="module")
-def device_full_ref():
+def _device_full_ref(N):
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_cnt17_N400_c512_r1536.npz")
+    path = os.path.join(os.path.dirname(__file__), "golden", f"oracle_cnt17_N{N}_c512_r1536.npz")
     d = np.load(path)
-    return W.device_problem(N=400), d["charge"], d["T"], float(d["current"][0])
+    return W.device_problem(N=N), d["charge"], d["T"], float(d["current"][0])
 
 
+@pytest.mark.parametrize("N", [400, 1000, 2000])
 @pytest.mark.parametrize("mode", ["FP64", "FP32_BULK"])
-def test_device_problem_full_grid_vs_oracle(gpu_lib, device_full_ref, mode):
-    """The bench's workload and launch shape, every output against the oracle's full run
-    (written by tests/golden/make_device_reference.py, which calls only the oracle)."""
-    p, q_ref, T_ref, c_ref = device_full_ref
+def test_device_problem_full_grid_vs_oracle(gpu_lib, mode, N):
+    """The (17,0) barrier workload at 400, 1000 and 2000 rings in the bench's launch
+    shape, every output against the oracle's full run (written by
+    tests/golden/make_device_reference.py, which calls only the oracle)."""
+    p, q_ref, T_ref, c_ref = _device_full_ref(N)
     got = gpu_lib.solve_problem(p, precision=getattr(gpu_lib, mode))
     e_q = rel(got.charge, q_ref)
     e_c = abs(got.current - c_ref) / abs(c_ref)
     e_T = rel(got.T, T_ref, floor=1e-8 * np.max(T_ref))
-    say(f"  full grid {mode}: charge rel {e_q:.3e} current rel {e_c:.3e} T rel {e_T:.3e}")
+    say(f"  full grid N={N} {mode}: charge rel {e_q:.3e} current rel {e_c:.3e} T rel {e_T:.3e}, "
+        f"{got.fp64_nodes} nodes in FP64")
     if mode == "FP64":
         assert e_q < 1e-10 and e_c < 1e-10 and e_T < 1e-9
-    else:   # measured, reported: current and T meet the bounds, per-atom charge does not
-        assert np.isfinite(e_q) and e_c < 1e-5 and e_T < 1e-3
+    else:
+        assert e_q < FP32_BULK_BOUND and e_c < FP32_BULK_BOUND and e_T < 1e-3
+        assert got.fp64_nodes <= p.grid.n_r // 5
 
 
 @pytest.mark.parametrize("mode", ["FP64", "FP32_BULK"])
@@ -381,3 +383,20 @@ def test_device_pointer_path_matches_host_path(gpu_lib, device_sub, mode):
     assert np.array_equal(charge.cpu().numpy(), host.charge)
     assert np.array_equal(T.cpu().numpy(), host.T)
     assert float(cur.item()) == host.current
+
+
+def test_fp32_bulk_recomputed_nodes_equal_fp64(gpu_lib):
+    """With every real-axis node recomputed (policy 1) the FP32-bulk real-axis outputs are
+    the FP64 solve's, bit for bit: the recomputation runs the FP64 kernels on FP64 stores;
+    with none recomputed (policy 2) they differ."""
+    p = W.device_problem(N=64, n_c=0, n_r=48)
+    r64 = gpu_lib.solve_problem(p, details=True)
+    all64 = gpu_lib.solve_problem(p, precision=gpu_lib.FP32_BULK, details=True, fp64_recompute=1)
+    none = gpu_lib.solve_problem(p, precision=gpu_lib.FP32_BULK, details=True, fp64_recompute=2)
+    say(f"  recompute all: {all64.fp64_nodes} nodes; none: {none.fp64_nodes}")
+    assert all64.fp64_nodes == p.grid.n_r and none.fp64_nodes == 0
+    for a, b in ((all64.al_diag, r64.al_diag), (all64.ar_diag, r64.ar_diag), (all64.T, r64.T), (all64.T_rl, r64.T_rl)):
+        assert np.array_equal(a, b)
+    assert not np.array_equal(none.al_diag, r64.al_diag)
+    # T_RL equals T_LR up to O(eta) in FP64
+    assert np.max(np.abs(r64.T - r64.T_rl) / np.maximum(r64.T, 1e-300)) < 1e-4
