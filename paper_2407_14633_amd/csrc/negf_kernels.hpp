@@ -889,7 +889,9 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         stage_row<T, B>(wr, wi, St, r, act);
         wave_sync();
         double* aout = reinterpret_cast<double*>(J.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
-        double wmag = 0.0, amin = 0.0, amax = 0.0;   // this row's max |W_rj| and range of A_rr
+        // this row's max |W_rj| and range of A_rr along the chain, kept in LDS (the
+        // propagation holds every register)
+        double* trk = &s_chk[gsafe][0][0] + 4 * r;   // [wmag, amin, amax, -] of row r
 
         for (int s = 0; s < N; ++s) {
             const int n = lead ? N - 1 - s : s;
@@ -902,8 +904,9 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
                 for (int j = 0; j < B; ++j) { const cx<TS> v = gload(p + j); pr[j] = -T(v.re); pi[j] = -T(v.im); }
             }
+            double wm = 0.0;
 #pragma unroll
-            for (int j = 0; j < B; ++j) wmag = fmax(wmag, fabs(wr[j]) + fabs(wi[j]));
+            for (int j = 0; j < B; ++j) wm = fmax(wm, fabs(wr[j]) + fabs(wi[j]));
             // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j]).  Gamma does not
             // change along the chain; its offset is made opaque each step so that its
             // B*B reads are not hoisted out of the loop into (spilled) registers.
@@ -913,9 +916,18 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             asm volatile("" : "+v"(goff));
             const T acc = gcirc ? row_quad_circ<T, B>(wr, wi, &s_gam[0][0] + goff)
                                 : row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
-            if (act) gstore_s(aout + (size_t)n * B + r, acc);
-            amin = s == 0 ? acc : fmin(amin, acc);
-            amax = s == 0 ? acc : fmax(amax, acc);
+            if (act) {
+                gstore_s(aout + (size_t)n * B + r, acc);
+                if (s == 0) {
+                    trk[0] = wm;
+                    trk[1] = acc;
+                    trk[2] = acc;
+                } else {
+                    trk[0] = fmax(trk[0], wm);
+                    trk[1] = fmin(trk[1], acc);
+                    trk[2] = fmax(trk[2], acc);
+                }
+            }
             if (s == N - 1) break;
             // W_next[r][:] = -sum_k P[r][k] W[k][:],  P = y~_n (right) or x~_n (left)
             row_mul_pipe<T, B>(pr, pi, St, wr, wi);
@@ -950,20 +962,16 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         }
         // chain-wide sums and extremes in fixed order through LDS
         wave_sync();
-        if (act) {
-            s_chk[gsafe][0][r] = t;
-            s_chk[gsafe][1][r] = wmag;
-            s_chk[gsafe][2][r] = amin;
-            s_chk[gsafe][3][r] = amax;
-        }
+        if (act) trk[3] = t;
         wave_sync();
         if (act && r == 0) {
-            double tsum = 0.0, wm = 0.0, amn = s_chk[gsafe][2][0], amx = s_chk[gsafe][3][0];
+            const double* tk = &s_chk[gsafe][0][0];
+            double tsum = 0.0, wm = 0.0, amn = tk[1], amx = tk[2];
             for (int q = 0; q < B; ++q) {
-                tsum += s_chk[gsafe][0][q];
-                wm = fmax(wm, s_chk[gsafe][1][q]);
-                amn = fmin(amn, s_chk[gsafe][2][q]);
-                amx = fmax(amx, s_chk[gsafe][3][q]);
+                tsum += tk[4 * q + 3];
+                wm = fmax(wm, tk[4 * q + 0]);
+                amn = fmin(amn, tk[4 * q + 1]);
+                amx = fmax(amx, tk[4 * q + 2]);
             }
             gstore_s((lead == 1 ? J.Tout : J.Trl) + ir, tsum);
             gstore_s(J.amax + 2 * ir + lead, amx);
