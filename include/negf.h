@@ -89,7 +89,9 @@ typedef struct {
     double decim_tol;         /* stop when max |alpha_ij|, |beta_ij| < decim_tol (eV) */
     int decim_max_iter;       /* NEGF_ENOCONV beyond this many doubling steps        */
     double g_s;               /* spin degeneracy (2)                                 */
-    size_t workspace_bytes;   /* cap on the per-energy recursion store; 0 = default  */
+    size_t workspace_bytes;   /* cap on the two recursion stores together; 0 = default
+                                 (each: 30% of the free HBM when the handle is made,
+                                 between 8 and 64 GiB)                               */
 } negf_options;
 
 typedef struct { double mu_L, mu_R, kT_L, kT_R; } negf_bias;
@@ -255,7 +257,8 @@ typedef struct {
 
 /* Workspace for batches: recursion stores, per-node arrays and the job/span
  * tables, grown on demand and kept between solves.  store_bytes caps each of the
- * two recursion stores (0 = 8 GiB); node ranges that do not fit run in several
+ * two recursion stores (0 = 30% of the free HBM at creation, between 8 and 64 GiB);
+ * node ranges that do not fit run in several
  * chunks.  Solves on one workspace are serialised on the device (a solve on
  * another stream waits for the previous one); the tables are uploaded only when
  * the job list changes.  Not thread-safe. */
@@ -379,7 +382,7 @@ void negf_modes_destroy(negf_modes *m);
  *
  * Admission: first come first served while the estimated HBM footprint of the
  * running requests fits hbm_budget minus the two recursion stores
- * (2 x store_bytes, 0 = 8 GiB each); at most max_inflight run at once.  A request
+ * (2 x store_bytes, 0 = the workspace default each); at most max_inflight run at once.  A request
  * whose footprint alone exceeds the budget is refused at submission (ENOMEM).
  * Submission copies every array.  The server's thread owns the GPU work on the
  * device that was current at creation; all calls are thread-safe.

@@ -233,7 +233,8 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     if (w->arena) {   // every buffer is placed afresh in the fixed area
         DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,   &w->iters, &w->status,
                         &w->coef_c, &w->coef_r,   &w->T,       &w->gr,      &w->ad,    &w->part, &w->Trl, &w->amax,
-                        &w->store_f, &w->store_b, &w->scratch, &w->flags, &w->fp64_spans, &w->fp64_first};
+                        &w->store_f, &w->store_b, &w->scratch, &w->flags, &w->fp64_spans, &w->fp64_first,
+                        &w->fp64_all, &w->fp64_ctl};
         for (DBuf* b : bufs) *b = DBuf{};
         w->arena_off = 0;
         w->last_tables.clear();
@@ -405,7 +406,9 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         long long cap;   // fp64 == 1: FP64 store elements the chunk's store holds
     };
     std::vector<int> nfirsts;       // node prefixes of the column spans of k_fp64_list launches
-    long long fp64_max = 0;         // longest node list of one chunk
+    std::vector<std::vector<negf::Span>> gcol(groups.size());   // FP32 groups: every column span
+    std::vector<size_t> gdyn64(groups.size(), 0);
+    size_t fp64_all = 0, fp64_max = 0, node64_max = 0;
     std::vector<negf::Span> spans;
     std::vector<int> firsts;
     std::vector<Launch> launches;
@@ -429,7 +432,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
 
     size_t scratch_need = 16, store_need = 0;
     std::vector<int> dec_grid_cap(groups.size(), 0);   // dense one-ring decimation: workgroups its state is sized for
-    size_t store_cap = w->store_cap ? w->store_cap : kDefaultStoreCap;
+    size_t store_cap = w->store_cap ? w->store_cap : w->default_store_cap;
     // Arena mode: what is left after the per-node arrays, less a reserve for the
     // decimation state, the tables and the counters, is split between the two
     // recursion stores; a dense one-ring decimation runs on fewer workgroups so
@@ -440,7 +443,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         for (int i = 0; i < n_jobs; ++i) ne_all += (size_t)plan[i].ne;
         dec_budget = (size_t)16 << 20;
         const size_t tab_bound = (size_t)n_jobs * (sizeof(negf::JobDesc) + sizeof(negf::RedJob)) +
-                                 (5 * ne_all + 16 * (size_t)n_jobs + 64) * (sizeof(negf::Span) + 2 * sizeof(int)) +
+                                 (8 * ne_all + 16 * (size_t)n_jobs + 64) * (sizeof(negf::Span) + 2 * sizeof(int)) +
                                  16 * 256;
         const size_t used = (w->arena_off + 255) & ~size_t(255);
         const size_t reserve = dec_budget + tab_bound;
@@ -453,7 +456,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         const size_t cb = g.f32 ? 8 : 16;   // bytes per store element
         // bytes of store reserved per element: with every real node recomputed in
         // FP64 the FP32 chunk's store must hold all of them in FP64
-        const size_t cbs = g.f32 && w->fp64_policy == 1 ? 16 : cb;
+        const size_t cbs = cb;
         // a1: decimation at every node.  One-ring and two-ring principal layers
         // have their own kernels; a job whose leads share the layer size runs
         // both leads in one span (sides 2), otherwise each lead in its own launch.
@@ -492,10 +495,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         }
         if (decimation_only) continue;
         // a3-a5: chunks of nodes whose recursion store fits the cap
-        size_t dyn = 0, dyn64 = 0;
+        size_t dyn = 0;
         for (int j : g.ids) {
             dyn = std::max(dyn, (size_t)jd[j].n_uniq * B * jd[j].K * (cb + 1));
-            dyn64 = std::max(dyn64, (size_t)jd[j].n_uniq * B * jd[j].K * 17);
+            gdyn64[gi] = std::max(gdyn64[gi], (size_t)jd[j].n_uniq * B * jd[j].K * 17);
         }
         size_t ji = 0;
         int e_at = 0;
@@ -537,23 +540,53 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
             TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, G, true, 0));
             TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, G, false,
                            0));
-            if (g.f32 && !col.empty()) {
-                // FP32-bulk: the real-axis nodes whose FP32 results the lead columns
-                // marked are recomputed in FP64 in the chunk's (now free) store
-                long long nreal = 0;
-                Launch LL{negf::KIND_COUNT, KT_COLUMN, gi, spans.size() - col.size(), nfirsts.size(),
-                          (int)col.size(), 1, 0, 0, 0, 1, (long long)(used * cbs / 16)};
-                for (const auto& x : col) {
-                    nfirsts.push_back((int)nreal);
-                    nreal += x.cnt;
-                }
-                nfirsts.push_back((int)nreal);
-                LL.units = nreal;
-                launches.push_back(LL);
-                fp64_max = std::max(fp64_max, nreal);
-                launches.push_back(Launch{negf::KIND_RECUR64, KT_RECUR, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, dyn64, 2, 0});
-                launches.push_back(Launch{negf::KIND_COLUMN64, KT_COLUMN, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0});
-            }
+            if (g.f32) gcol[gi].insert(gcol[gi].end(), col.begin(), col.end());
+        }
+    }
+    // FP32-bulk: after every group's chunks, the real-axis nodes whose FP32 results
+    // are doubtful are recomputed in FP64 in the (now free) recursion stores, in
+    // rounds of what the stores hold.  The rounds cover a quarter of the real-axis
+    // nodes' FP64 stores (all of them when every node is recomputed); nodes beyond
+    // that are an error.
+    std::vector<size_t> gall(groups.size(), 0);   // offset of each group's node list
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        if (gcol[gi].empty()) continue;
+        const int B = groups[gi].L->B;
+        long long nreal = 0;
+        for (const auto& x : gcol[gi]) {
+            nreal += x.cnt;
+            node64_max = std::max(node64_max, (size_t)jd[x.job].N * B * B * 16);
+        }
+        gall[gi] = fp64_all;
+        fp64_all += (size_t)nreal;
+        fp64_max = std::max(fp64_max, (size_t)nreal);
+    }
+    store_need = std::max(store_need, node64_max);
+    const long long cap64 = (long long)(store_need / 16);
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        if (gcol[gi].empty()) continue;
+        const int B = groups[gi].L->B;
+        double elems = 0.0;
+        long long nreal = 0;
+        Launch LL{negf::KIND_COUNT, KT_COLUMN, gi, spans.size(), nfirsts.size(), (int)gcol[gi].size(), 1, 0, 0, 0, 1,
+                  (long long)gall[gi]};
+        for (const auto& x : gcol[gi]) {
+            nfirsts.push_back((int)nreal);
+            nreal += x.cnt;
+            elems += (double)x.cnt * jd[x.job].N * B * B;
+            spans.push_back(x);
+        }
+        nfirsts.push_back((int)nreal);
+        LL.units = nreal;
+        launches.push_back(LL);
+        const double frac = w->fp64_policy == 1 ? 1.0 : 0.25;
+        const long long per = (long long)(store_need / 16) - (long long)(node64_max / 16);   // fill guaranteed per round
+        const int rounds = 1 + (int)std::ceil(frac * elems / (double)std::max<long long>(per, 1));
+        for (int r = 0; r < rounds; ++r) {
+            launches.push_back(Launch{negf::KIND_COUNT, KT_COLUMN, gi, 0, 0, (int)nreal, 1, 0, nreal, 0, 3,
+                                      r == rounds - 1 ? -cap64 : cap64});
+            launches.push_back(Launch{negf::KIND_RECUR64, KT_RECUR, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0});
+            launches.push_back(Launch{negf::KIND_COLUMN64, KT_COLUMN, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0});
         }
     }
     TRY(grow(w, w->scratch, scratch_need));
@@ -564,8 +597,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     const size_t n_counters = std::max<size_t>(1, launches.size());
     TRY(grow(w, w->counters, n_counters * 4));
     if (fp64_max) {
-        TRY(grow(w, w->fp64_spans, (size_t)fp64_max * sizeof(negf::Span)));
-        TRY(grow(w, w->fp64_first, (size_t)(fp64_max + 1) * sizeof(int)));
+        TRY(grow(w, w->fp64_all, fp64_all * sizeof(negf::Span)));
+        TRY(grow(w, w->fp64_spans, fp64_max * sizeof(negf::Span)));
+        TRY(grow(w, w->fp64_first, (fp64_max + 1) * sizeof(int)));
+        TRY(grow(w, w->fp64_ctl, groups.size() * 2 * sizeof(int)));
     }
 
     // ---- tables: one image [JobDesc][RedJob][Span][first], uploaded only when it
@@ -597,6 +632,8 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     const int* d_nfirst = reinterpret_cast<const int*>(tab + o_nf);
     negf::Span* d_fp64_spans = static_cast<negf::Span*>(w->fp64_spans.p);
     int* d_fp64_first = static_cast<int*>(w->fp64_first.p);
+    negf::Span* d_fp64_all = static_cast<negf::Span*>(w->fp64_all.p);
+    int* d_fp64_ctl = static_cast<int*>(w->fp64_ctl.p);   // per group: listed nodes, cursor
 
     hipEvent_t ev;
     ev_begin(w, s, &ev);
@@ -606,13 +643,22 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                        static_cast<int*>(w->status.p), (int)nodes);
     ev_end(w, KT_REDUCE, s, ev);
 
+    const negf::Span* cur_all = nullptr;   // node list of the group being recomputed
     for (size_t li = 0; li < launches.size(); ++li) {
         const Launch& L = launches[li];
         const Group& g = groups[L.group];
-        if (L.fp64 == 1) {
+        if (L.fp64 == 1) {   // list of the group's nodes to recompute; the cursor is reset
+            int* ctl = d_fp64_ctl + 2 * L.group;
+            hipLaunchKernelGGL(negf::k_fill_int, dim3(1), dim3(64), 0, s, ctl + 1, 1, 0);
             hipLaunchKernelGGL(negf::k_fp64_list, dim3(1), dim3(1024), 0, s, d_jobs, d_red, d_spans + L.span_at,
-                               d_nfirst + L.first_at, L.n_spans, g.L->B, L.cap, d_fp64_spans, d_fp64_first,
-                               (int)L.units);
+                               d_nfirst + L.first_at, L.n_spans, g.L->B, d_fp64_all + L.cap, ctl);
+            cur_all = d_fp64_all + L.cap;
+            continue;
+        }
+        if (L.fp64 == 3) {   // the next round of the list that fits the stores
+            int* ctl = d_fp64_ctl + 2 * L.group;
+            hipLaunchKernelGGL(negf::k_fp64_round, dim3(1), dim3(1024), 0, s, d_jobs, cur_all, ctl, ctl + 1, g.L->B,
+                               L.cap < 0 ? -L.cap : L.cap, d_fp64_spans, d_fp64_first, L.n_spans, L.cap < 0 ? 1 : 0);
             continue;
         }
         negf::Sched S{};
@@ -695,6 +741,14 @@ negf_status ws_create(negf_workspace** out, size_t store_bytes) {
         return fail(NEGF_EHIP, "no HIP device");
     }
     w->cus = prop.multiProcessorCount;
+    // default recursion-store cap per direction: 30 % of the free HBM at creation,
+    // between 8 and 64 GiB, so that long batches run in few large chunks
+    {
+        size_t fr = 0, tot = 0;
+        w->default_store_cap = kDefaultStoreCap;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+            w->default_store_cap = std::min<size_t>((size_t)64 << 30, std::max<size_t>(kDefaultStoreCap, fr / 10 * 3));
+    }
     if (hipStreamCreateWithFlags(&w->own_stream, hipStreamNonBlocking) != hipSuccess) {
         delete w;
         return fail(NEGF_EHIP, "stream creation failed");
@@ -726,7 +780,7 @@ void ws_destroy(negf_workspace* w) {
     }
     DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,  &w->iters,      &w->status,
                     &w->coef_c, &w->coef_r,   &w->T,       &w->gr,     &w->ad,         &w->part, &w->Trl, &w->amax,
-                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc, &w->fp64_spans, &w->fp64_first,
+                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc, &w->fp64_spans, &w->fp64_first, &w->fp64_all, &w->fp64_ctl,
                     &w->in_Er,  &w->in_wr,    &w->out_charge, &w->out_T, &w->out_cur};
     for (DBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);

@@ -68,9 +68,10 @@ using negf_host::kFlagInts;
 struct negf_workspace {
     int dev_id = 0;
     size_t store_cap = 0;     // bytes per recursion store direction; 0 = default
+    size_t default_store_cap = (size_t)8 << 30;   // set at creation from the free HBM
     int cus = 0;
     DBuf tables, counters, z, sigma, iters, status, coef_c, coef_r, T, gr, ad, part, store_f, store_b, scratch,
-        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur, fp64_spans, fp64_first, Trl, amax;
+        flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur, fp64_spans, fp64_first, Trl, amax, fp64_all, fp64_ctl;
     std::vector<char> last_tables;   // host image of `tables` (re-uploaded only when it changes)
     hipEvent_t done = nullptr;       // recorded after each enqueued solve
     int* h_flags = nullptr;   // pinned [2 * cap_flags]

@@ -195,33 +195,29 @@ __global__ __launch_bounds__(64) void k_current(const RedJob* jobs) {
 #define NEGF_FP32_QTOL 1e-7
 #endif
 
-// FP32-bulk, after the lead columns of one chunk: the real-axis nodes to recompute
-// in FP64.  A node is taken when the lead columns marked it (ST_FP64), or when its
-// two transmissions disagree by more than its weight allows: T_LR comes from the
-// right lead column (forward recursion), T_RL from the left one (backward
-// recursion), and they agree up to O(eta) unless an FP32 recursion lost digits;
-// with r = |T_LR - T_RL| / max(T_LR, T_RL) and the node's largest charge term
-// c = g_s (|w|/pi) (f_L max_i A_L,ii + f_R max_i A_R,ii), the node is taken when
-// c sqrt(r) > NEGF_FP32_QTOL (sqrt(r): the spectral densities were measured to be
-// off by up to ~100 r on the nanotube workloads).  The taken nodes get slots of
-// FP64 recursion store in node order while the slots fit the chunk's store (cap
-// FP64 elements, the FP32 data being dead by then); each becomes a one-node span
-// of the FP64 recursion and column launches that follow (units: two per span,
-// directions or leads).  A taken node that does not fit is marked ST_NOROOM.
-// col[0..n_col) are the chunk's column spans, col_first their node prefix.  One
-// workgroup of 1024 threads; the order is that of the nodes.
+// FP32-bulk, after the lead columns of every chunk of one kernel group: the
+// real-axis nodes to recompute in FP64.  A node is taken when the lead columns
+// marked it (ST_FP64), or when its two transmissions disagree by more than its
+// weight allows: T_LR comes from the right lead column (forward recursion), T_RL
+// from the left one (backward recursion), and they agree up to O(eta) unless an
+// FP32 recursion lost digits; with r = |T_LR - T_RL| / max(T_LR, T_RL) and the
+// node's largest charge term c = g_s (|w|/pi) (f_L max_i A_L,ii + f_R max_i A_R,ii)
+// the node is taken when c sqrt(r) > NEGF_FP32_QTOL (sqrt(r): the spectral
+// densities were measured to be off by up to ~100 r on the nanotube workloads).
+// The taken nodes are listed in node order as one-node spans whose `off` is the
+// running sum of their FP64 store sizes (N b^2 elements each); *count receives
+// their number.  col[0..n_col) are the group's column spans, col_first their node
+// prefix.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const RedJob* red, const Span* col,
-                                                   const int* col_first, int n_col, int B, long long cap, Span* out,
-                                                   int* out_first, int max_out) {
+                                                   const int* col_first, int n_col, int B, Span* all, int* count) {
     __shared__ long long s_sz[1024];
     __shared__ int s_ct[1024];
     __shared__ long long s_base;
-    __shared__ int s_seen, s_emit;
+    __shared__ int s_seen;
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_base = 0;
         s_seen = 0;
-        s_emit = 0;
     }
     __syncthreads();
     const int total = col_first[n_col];
@@ -249,10 +245,10 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
                              (fermi_real(E, R.mu_L, R.kT_L) * J.amax[2 * ir] +
                               fermi_real(E, R.mu_R, R.kT_R) * J.amax[2 * ir + 1]);
             const bool recip = !(c * sqrt(r) <= NEGF_FP32_QTOL);
-            const bool mark = J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e] & ST_FP64) || recip));
-            if (mark) {
+            const bool take = J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e] & ST_FP64) || recip));
+            if (take) {
                 ct = 1;
-                sz = (long long)jobs[job].N * B * B;
+                sz = (long long)J.N * B * B;
             }
         }
         s_sz[tid] = sz;
@@ -266,18 +262,7 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
             s_ct[tid] += c;
             __syncthreads();
         }
-        if (ct) {
-            // offsets grow with the node order, so the nodes that fit are a prefix
-            const long long off = s_base + s_sz[tid] - sz;
-            const int idx = s_seen + s_ct[tid] - 1;
-            if (off + sz <= cap && idx < max_out) {
-                out[idx] = Span{job, e, 1, 0, off};
-                atomicAdd(jobs[job].n_fp64, 1);
-                atomicAdd(&s_emit, 1);
-            } else {
-                atomicOr(&jobs[job].status[e], (int)ST_NOROOM);
-            }
-        }
+        if (ct) all[s_seen + s_ct[tid] - 1] = Span{job, e, 1, 0, s_base + s_sz[tid] - sz};
         __syncthreads();
         if (tid == 0) {
             s_base += s_sz[1023];
@@ -285,7 +270,48 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
         }
         __syncthreads();
     }
-    for (int k = tid; k <= max_out; k += 1024) out_first[k] = 2 * min(k, s_emit);
+    if (tid == 0) *count = s_seen;
+}
+
+// One round of FP64 recomputation: the listed nodes from *cursor on whose FP64
+// stores fit `cap` elements (a prefix, the store offsets growing along the list)
+// become the spans of this round, with offsets relative to the round's first
+// node; the unit prefix out_first[k] = 2 min(k, taken) serves the recursion
+// (two directions) and the lead-column launches (two leads).  The cursor moves
+// past them; on the last round the nodes left are marked ST_NOROOM.  One
+// workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_fp64_round(const JobDesc* jobs, const Span* all, const int* count,
+                                                    int* cursor, int B, long long cap, Span* out, int* out_first,
+                                                    int max_out, int last) {
+    __shared__ int s_take;
+    const int tid = threadIdx.x;
+    const int n = *count, c0 = *cursor;
+    const long long base = c0 < n ? all[c0].off : 0;
+    if (tid == 0) {
+        // largest m with end(c0 + m - 1) - base <= cap, by bisection on the monotone ends
+        int lo = 0, hi = min(n - c0, max_out);   // m in [lo, hi]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            const Span sp = all[c0 + mid - 1];
+            const long long end = sp.off + (long long)jobs[sp.job].N * B * B;
+            if (end - base <= cap) lo = mid; else hi = mid - 1;
+        }
+        s_take = lo;
+    }
+    __syncthreads();
+    const int m = s_take;
+    for (int k = tid; k < m; k += 1024) {
+        Span sp = all[c0 + k];
+        sp.off -= base;
+        out[k] = sp;
+        atomicAdd(jobs[sp.job].n_fp64, 1);
+    }
+    for (int k = tid; k <= max_out; k += 1024) out_first[k] = 2 * min(k, m);
+    if (last) {
+        for (int k = c0 + m + tid; k < n; k += 1024) atomicOr(&jobs[all[k].job].status[all[k].e0], (int)ST_NOROOM);
+    }
+    __syncthreads();
+    if (tid == 0) *cursor = c0 + m;
 }
 
 __global__ void k_fill_int(int* p, int n, int v) {

@@ -364,7 +364,7 @@ negf_status negf_server_create(negf_server** out, size_t hbm_budget, int max_inf
     S->max_inflight = max_inflight;
     negf_status st;
     if ((st = ws_create(&S->ws, store_bytes)) != NEGF_OK) return bail(st);
-    const size_t cap = store_bytes ? store_bytes : ((size_t)8 << 30);
+    const size_t cap = store_bytes ? store_bytes : S->ws->default_store_cap;
     S->fixed = 2 * cap;
     if (hbm_budget <= S->fixed) return bail(fail(NEGF_EINVAL, "budget %zu bytes leaves nothing beyond the two "
                                                              "recursion stores (%zu bytes)", hbm_budget, S->fixed));
