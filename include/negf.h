@@ -287,9 +287,16 @@ typedef struct {
     int grid_scale;        /* persistent workgroups per (resident workgroups x CUs) */
     int order;
     double ms_per_solve;   /* autotuner: measured time of the chosen setting        */
+    int chains_per_wave[NEGF_MAX_RING + 1];   /* autotuner: chosen chains per wavefront
+                              for each ring size b of the jobs (64/b: tiles of b-lane
+                              chains; 1: one wavefront per energy node); 0 for ring
+                              sizes not in the jobs                                  */
 } negf_schedule;
 
 negf_status negf_workspace_set_order(negf_workspace *w, int order);
+/* Chains per wavefront for the recursions, contour diagonals and lead columns of
+ * ring size b: 1..64/b (a chain is one node's recursion on b lanes), 0 = 64/b. */
+negf_status negf_workspace_set_chains_per_wave(negf_workspace *w, int b, int chains);
 /* negf_set_fp64_recompute for the FP32-bulk jobs of a workspace's batches. */
 negf_status negf_workspace_set_fp64_recompute(negf_workspace *w, int policy);
 /* Basis of the lead decimation (Section 2.2.2).  1 (default): a lead whose
@@ -303,8 +310,10 @@ negf_status negf_workspace_set_fp64_recompute(negf_workspace *w, int policy);
  * that reuses a self-energy cache (sigma_mode 2) should run with the basis the
  * cache was filled with (otherwise its results move at the rounding level). */
 negf_status negf_workspace_set_lead_basis(negf_workspace *w, int ring_modes);
-/* Times every schedule setting on this job list (reps solves each, device
- * pointers, on hip_stream), keeps the fastest in w and returns it in *best. */
+/* Times the schedule settings on this job list (reps solves each, device
+ * pointers, on hip_stream): persistent grid scale {1, 2, 4} x job order, then,
+ * per ring size present, chains per wavefront {64/b, half of that, 1}; keeps the
+ * fastest in w and returns it in *best. */
 negf_status negf_workspace_autotune(negf_workspace *w, int n_jobs, const negf_job *jobs, void *hip_stream,
                                     int reps, negf_schedule *best);
 

@@ -402,8 +402,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         int n_spans, sides, side0;
         long long units;
         size_t dyn;
-        int fp64;        // 1: k_fp64_list over a chunk's column spans; 2: a launch over its node list
-        long long cap;   // fp64 == 1: FP64 store elements the chunk's store holds
+        int fp64;        // 1: k_fp64_list over a group's column spans; 3: one recomputation round;
+                         // 2: a launch over the round's node list
+        long long cap;   // fp64 == 1: offset of the group's node list; 3: FP64 store elements (< 0: last round)
+        int gpw;         // nodes (or items) per unit
     };
     std::vector<int> nfirsts;       // node prefixes of the column spans of k_fp64_list launches
     std::vector<std::vector<negf::Span>> gcol(groups.size());   // FP32 groups: every column span
@@ -415,7 +417,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     auto add_launch = [&](int kind, int kt, int gidx, const std::vector<negf::Span>& sp, int sides, int side0,
                           int G, bool items, size_t dyn) -> negf_status {
         if (sp.empty()) return NEGF_OK;
-        Launch L{kind, kt, gidx, spans.size(), firsts.size(), (int)sp.size(), sides, side0, 0, dyn, 0, 0};
+        Launch L{kind, kt, gidx, spans.size(), firsts.size(), (int)sp.size(), sides, side0, 0, dyn, 0, 0, G};
         long long acc = 0;
         for (const auto& x : sp) {
             firsts.push_back((int)acc);
@@ -453,6 +455,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
         Group& g = groups[gi];
         const int B = g.L->B, G = g.L->groups;
+        const int gpw = w->gpw_b[B] > 0 ? std::min(w->gpw_b[B], G) : G;   // chains per wavefront
         const size_t cb = g.f32 ? 8 : 16;   // bytes per store element
         // bytes of store reserved per element: with every real node recomputed in
         // FP64 the FP32 chunk's store must hold all of them in FP64
@@ -536,9 +539,9 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                 }
             }
             store_need = std::max(store_need, used * cbs);
-            TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, rec, 2, 0, G, false, dyn));
-            TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, G, true, 0));
-            TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, G, false,
+            TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, rec, 2, 0, gpw, false, dyn));
+            TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, gpw, true, 0));
+            TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, gpw, false,
                            0));
             if (g.f32) gcol[gi].insert(gcol[gi].end(), col.begin(), col.end());
         }
@@ -569,7 +572,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         double elems = 0.0;
         long long nreal = 0;
         Launch LL{negf::KIND_COUNT, KT_COLUMN, gi, spans.size(), nfirsts.size(), (int)gcol[gi].size(), 1, 0, 0, 0, 1,
-                  (long long)gall[gi]};
+                  (long long)gall[gi], 1};
         for (const auto& x : gcol[gi]) {
             nfirsts.push_back((int)nreal);
             nreal += x.cnt;
@@ -584,9 +587,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         const int rounds = 1 + (int)std::ceil(frac * elems / (double)std::max<long long>(per, 1));
         for (int r = 0; r < rounds; ++r) {
             launches.push_back(Launch{negf::KIND_COUNT, KT_COLUMN, gi, 0, 0, (int)nreal, 1, 0, nreal, 0, 3,
-                                      r == rounds - 1 ? -cap64 : cap64});
-            launches.push_back(Launch{negf::KIND_RECUR64, KT_RECUR, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0});
-            launches.push_back(Launch{negf::KIND_COLUMN64, KT_COLUMN, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0});
+                                      r == rounds - 1 ? -cap64 : cap64, 1});
+            launches.push_back(
+                Launch{negf::KIND_RECUR64, KT_RECUR, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0, 1});
+            launches.push_back(Launch{negf::KIND_COLUMN64, KT_COLUMN, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0, 1});
         }
     }
     TRY(grow(w, w->scratch, scratch_need));
@@ -674,6 +678,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         S.scratch = static_cast<cx<double>*>(w->scratch.p);
         S.tol = g.tol;
         S.maxit = g.maxit;
+        S.gpw = L.gpw;
         int grid = persistent_grid(w, g.L->func[L.kind], L.dyn, L.units);
         if (L.kind == negf::KIND_DECIMATE && dec_grid_cap[L.group] > 0) grid = std::min(grid, dec_grid_cap[L.group]);
         ev_begin(w, s, &ev);
@@ -1315,6 +1320,14 @@ negf_status negf_set_fp64_recompute(negf_device* d, int policy) {
     return negf_workspace_set_fp64_recompute(d->ws, policy);
 }
 
+negf_status negf_workspace_set_chains_per_wave(negf_workspace* w, int b, int chains) {
+    if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
+    if (b < 1 || b > NEGF_MAX_RING) return fail(NEGF_EINVAL, "ring size %d not in [1,%d]", b, NEGF_MAX_RING);
+    if (chains < 0 || chains > 64 / b) return fail(NEGF_EINVAL, "chains per wavefront %d not in [0,%d]", chains, 64 / b);
+    w->gpw_b[b] = chains;
+    return NEGF_OK;
+}
+
 negf_status negf_workspace_set_order(negf_workspace* w, int order) {
     if (!w) return fail(NEGF_EINVAL, "workspace is NULL");
     if (order != 0 && order != 1) return fail(NEGF_EINVAL, "order must be 0 or 1");
@@ -1341,31 +1354,64 @@ negf_status negf_workspace_autotune(negf_workspace* w, int n_jobs, const negf_jo
     hipEvent_t t0, t1;
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
-    const int scales[] = {1, 2, 4};
-    negf_schedule bs{1, 0, 0.0};
     negf_status st = NEGF_OK;
+    // mean time of `reps` solves with the workspace's current settings
+    auto timed = [&](double* ms_out) -> negf_status {
+        negf_status e;
+        if ((e = enqueue(w, n_jobs, jobs, s)) != NEGF_OK || (e = finish(w, nullptr)) != NEGF_OK) return e;
+        (void)hipEventRecord(t0, s);
+        for (int r = 0; r < reps && e == NEGF_OK; ++r) e = enqueue(w, n_jobs, jobs, s);
+        (void)hipEventRecord(t1, s);
+        if (e == NEGF_OK) e = finish(w, nullptr);
+        if (e != NEGF_OK) return e;
+        float ms = 0.f;
+        if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess)
+            return fail(NEGF_EHIP, "autotune timing events failed");
+        *ms_out = ms / reps;
+        return NEGF_OK;
+    };
+    negf_schedule bs{};
+    bs.grid_scale = 1;
+    // family 1: persistent grid size x job order, every ring size at full chains per wavefront
+    for (int b = 0; b <= NEGF_MAX_RING; ++b) w->gpw_b[b] = 0;
+    const int scales[] = {1, 2, 4};
     for (int order = 0; order < 2 && st == NEGF_OK; ++order)
         for (int sc : scales) {
             w->grid_scale = sc;
             w->order = order;
-            if ((st = enqueue(w, n_jobs, jobs, s)) != NEGF_OK || (st = finish(w, nullptr)) != NEGF_OK) break;
-            (void)hipEventRecord(t0, s);
-            for (int r = 0; r < reps && st == NEGF_OK; ++r) st = enqueue(w, n_jobs, jobs, s);
-            (void)hipEventRecord(t1, s);
-            if (st == NEGF_OK) st = finish(w, nullptr);
-            if (st != NEGF_OK) break;
-            float ms = 0.f;
-            if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
-                st = fail(NEGF_EHIP, "autotune timing events failed");
-                break;
+            double per = 0.0;
+            if ((st = timed(&per)) != NEGF_OK) break;
+            if (bs.ms_per_solve == 0.0 || per < bs.ms_per_solve) {
+                bs.grid_scale = sc;
+                bs.order = order;
+                bs.ms_per_solve = per;
             }
-            const double per = ms / reps;
-            if (bs.ms_per_solve == 0.0 || per < bs.ms_per_solve) bs = negf_schedule{sc, order, per};
         }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     w->grid_scale = bs.grid_scale;
     w->order = bs.order;
+    // family 2: chains per wavefront, per ring size (coordinate descent over the ring
+    // sizes present): all that fit (the tile schedule), half of them, or one (a
+    // wavefront per energy node)
+    bool present[NEGF_MAX_RING + 1] = {false};
+    for (int i = 0; i < n_jobs; ++i) present[jobs[i].dev->b] = true;
+    for (int b = 1; b <= NEGF_MAX_RING && st == NEGF_OK; ++b) {
+        bs.chains_per_wave[b] = present[b] ? 64 / b : 0;
+        if (!present[b] || 64 / b < 2) continue;
+        const int cand[2] = {(64 / b + 1) / 2, 1};
+        for (int c : cand) {
+            if (c == 64 / b) continue;
+            w->gpw_b[b] = c;
+            double per = 0.0;
+            if ((st = timed(&per)) != NEGF_OK) break;
+            if (per < bs.ms_per_solve) {
+                bs.ms_per_solve = per;
+                bs.chains_per_wave[b] = c;
+            }
+        }
+        w->gpw_b[b] = bs.chains_per_wave[b] == 64 / b ? 0 : bs.chains_per_wave[b];
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
     if (best) *best = bs;
     return st;
 }

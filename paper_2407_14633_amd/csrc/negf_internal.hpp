@@ -92,6 +92,7 @@ struct negf_workspace {
     int order = 0;            // 0: longest chains first, 1: jobs in the caller's order
     bool circ_decimation = true;   // ring-circulant leads decimated in the ring Fourier basis
     int fp64_policy = 0;      // FP32-bulk real nodes recomputed in FP64: 0 marked ones, 1 all, 2 none
+    int gpw_b[NEGF_MAX_RING + 1] = {0};   // chains per wavefront by ring size (0: as many as fit)
     bool capturing = false;   // enqueue is being recorded into a graph
     // Arena mode (allocation-free solves): every buffer is carved from [arena,
     // arena + arena_cap) at each enqueue instead of being grown with hipMalloc.

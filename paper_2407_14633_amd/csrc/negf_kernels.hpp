@@ -484,6 +484,9 @@ struct Sched {
     int sides;                // sides per span: 2 (both directions / leads) or 1
     int side0;                // first side (1 = backward direction / right lead alone)
     int* counter;             // zero before launch
+    int gpw;                  // nodes per unit (recursions, lead columns) or (node, ring) items
+                              // per unit (contour diagonals): at most the chains one
+                              // wavefront holds; fewer leave groups of lanes idle
     void* store_f;            // recursion stores: slot n = y~_n (real) / y_n (contour); slot 0 = G_{N-1,N-1}
     void* store_b;            //                   slot n = x~_n (real) / x_n (contour); slot N-1 = G_00
     cx<double>* scratch;      // decimation state, per workgroup: G chains x 6 b x b blocks
@@ -515,15 +518,15 @@ __device__ __forceinline__ bool next_unit(const Sched& S, Unit& u, bool items = 
     u.side = S.side0 + local % S.sides;
     const int blk = local / S.sides;
     if (items) {                          // k_cdiag: G (node, ring) items
-        u.i0 = blk * G;
+        u.i0 = blk * S.gpw;
         u.e0 = sp.e0;
         u.off = sp.off;
         u.cnt = 0;                        // set by the caller from N
     } else {
-        u.e0 = sp.e0 + blk * G;
-        u.cnt = min(G, sp.e0 + sp.cnt - u.e0);
+        u.e0 = sp.e0 + blk * S.gpw;
+        u.cnt = min(S.gpw, sp.e0 + sp.cnt - u.e0);
         u.off = sp.off;
-        u.i0 = blk * G;                   // node offset of the unit inside the span
+        u.i0 = blk * S.gpw;               // node offset of the unit inside the span
     }
     return true;
 }
@@ -543,7 +546,11 @@ __device__ __forceinline__ void stage_to_global(const cx<T>* S, cx<T>* dst, int 
 }
 
 // a_n row r into (xr, xi), optionally minus m:  z - H_nn - U_n - [n==0] Sigma_L - [n==N-1] Sigma_R
-template <typename T, int B>
+// kDiag: how z - u reaches the diagonal entry.  0: a branch per entry; 1: a select on
+// every entry (with a branch per entry the compiler may merge the cases into a
+// pointer choice that keeps the row in scratch memory, as it does in k_cdiag for
+// the larger ring sizes); 2: not at all (the caller has put it on the diagonal).
+template <typename T, int B, int kDiag = 0>
 __device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r, double u, cx<double> z,
                                           T (&xr)[B], T (&xi)[B]) {
     if (!J.hdiag_zero) {
@@ -552,9 +559,17 @@ __device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r,
         for (int j = 0; j < B; ++j) { const cx<double> hv = gload(h + j); xr[j] -= T(hv.re); xi[j] -= T(hv.im); }
     }
     const T dre = T(z.re - u), dim = T(z.im);   // diagonal formed in FP64, then rounded
+    if constexpr (kDiag == 0) {
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-        if (j == r) { xr[j] += dre; xi[j] += dim; }
+        for (int j = 0; j < B; ++j) {
+            if (j == r) { xr[j] += dre; xi[j] += dim; }
+        }
+    } else if constexpr (kDiag == 1) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            xr[j] += j == r ? dre : T(0);
+            xi[j] += j == r ? dim : T(0);
+        }
     }
     if (n == 0 || n == J.N - 1) {
 #pragma unroll
@@ -666,10 +681,16 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
                 }
             }
             if (!done64) {
+                // z - u goes onto the diagonal through the stage (this lane's own entry),
+                // so the row below is loaded without a per-entry diagonal test
+                if (act) {
+                    const cx<T> d = g.stage[r * B + r];
+                    g.stage[r * B + r] = cx<T>{d.re - T(z.re - uu), d.im - T(z.im)};
+                }
                 T kr[B], ki[B];
 #pragma unroll
                 for (int j = 0; j < B; ++j) { const cx<T> y = g.stage[r * B + j]; kr[j] = -y.re; ki[j] = -y.im; }
-                if (act) add_a_row<T, B>(J, e, n, r, uu, z, kr, ki);
+                if (act) add_a_row<T, B, 2>(J, e, n, r, uu, z, kr, ki);
                 gj_inverse<T, B>(kr, ki, g);   // (a_n - y_n)^{-1} -> stage
             }
             if (last) {
@@ -754,7 +775,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         const JobDesc& J = S.jobs[u.job];
         const int N = J.N;
         const int n_items = S.spans[u.span].cnt * N;
-        const bool live = (gi < G) && (u.i0 + gi < n_items);
+        const bool live = (gi < S.gpw) && (u.i0 + gi < n_items);
         const int item = u.i0 + (live ? gi : 0);
         const int el = item / N;                 // node inside the span
         const int e = u.e0 + el;                 // node inside the job
@@ -779,7 +800,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
                         for (int j = 0; j < B; ++j) { const cx<T> v = gload(sb + j); kr[j] -= v.re; ki[j] -= v.im; }
                     }
-                    add_a_row<double, B>(J, e, n, r, gload_s(J.U + (size_t)n * B + r), gload(J.z + e), kr, ki);
+                    add_a_row<double, B, 1>(J, e, n, r, gload_s(J.U + (size_t)n * B + r), gload(J.z + e), kr, ki);
                 }
                 Grp<double, B> g64{r, act64, s_stage64[gsafe], s_prow64[gsafe], s_keys[gsafe]};
                 gj_inverse<double, B>(kr, ki, g64);
@@ -808,7 +829,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
                 for (int j = 0; j < B; ++j) { const cx<T> v = gload(sb + j); kr[j] -= v.re; ki[j] -= v.im; }
             }
-            add_a_row<T, B>(J, e, n, r, gload_s(J.U + (size_t)n * B + r), gload(J.z + e), kr, ki);
+            add_a_row<T, B, 1>(J, e, n, r, gload_s(J.U + (size_t)n * B + r), gload(J.z + e), kr, ki);
         }
         gj_inverse<T, B>(kr, ki, g);
         if (act) {

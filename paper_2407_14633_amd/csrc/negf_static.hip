@@ -86,6 +86,7 @@ negf_status negf_solve_dev_static(negf_device* d, const negf_bias* bias, int n_c
     w.order = own->order;
     w.circ_decimation = own->circ_decimation;
     w.fp64_policy = own->fp64_policy;
+    for (int b = 0; b <= NEGF_MAX_RING; ++b) w.gpw_b[b] = own->gpw_b[b];
     w.arena = area;
     w.arena_cap = kScratchBytes;
     const negf_status st = enqueue(&w, 1, &j, (hipStream_t)hip_stream);

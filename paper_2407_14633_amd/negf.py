@@ -34,7 +34,7 @@ EXPORTED = [
     "negf_server_poll", "negf_server_stats", "negf_server_destroy", "negf_modes_create",
     "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy", "negf_semi_adaptive_grid",
     "negf_solve_dev_static", "negf_static_scratch_bytes", "negf_fp64_nodes", "negf_workspace_fp64_nodes",
-    "negf_set_fp64_recompute", "negf_workspace_set_fp64_recompute",
+    "negf_set_fp64_recompute", "negf_workspace_set_fp64_recompute", "negf_workspace_set_chains_per_wave",
 ]
 
 
@@ -76,7 +76,8 @@ class negf_job(C.Structure):
 
 
 class negf_schedule(C.Structure):
-    _fields_ = [("grid_scale", C.c_int), ("order", C.c_int), ("ms_per_solve", C.c_double)]
+    _fields_ = [("grid_scale", C.c_int), ("order", C.c_int), ("ms_per_solve", C.c_double),
+                ("chains_per_wave", C.c_int * 25)]
 
 
 class negf_sc_request(C.Structure):
@@ -121,6 +122,8 @@ def load(path: str = LIB_PATH):
     lib.negf_solve_ex.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, C.POINTER(negf_outputs)]
     lib.negf_solve_dev.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
     lib.negf_sync.argtypes = [vp]
+    lib.negf_workspace_set_chains_per_wave.argtypes = [vp, i, i]
+    lib.negf_workspace_set_chains_per_wave.restype = C.c_int
     lib.negf_set_fp64_recompute.argtypes = [vp, i]
     lib.negf_set_fp64_recompute.restype = C.c_int
     lib.negf_workspace_set_fp64_recompute.argtypes = [vp, i]
@@ -458,6 +461,10 @@ class Workspace:
         a = (C.c_int * max(1, n_jobs))()
         _check(load().negf_workspace_fp64_nodes(self.h, int(n_jobs), a))
         return [int(a[k]) for k in range(n_jobs)]
+
+    def set_chains_per_wave(self, b: int, chains: int):
+        """Chains per wavefront for ring size b (0: as many as fit)."""
+        _check(load().negf_workspace_set_chains_per_wave(self.h, int(b), int(chains)))
 
     def set_order(self, order: int):
         _check(load().negf_workspace_set_order(self.h, int(order)))
