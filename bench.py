@@ -70,12 +70,12 @@ def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
     flops; a dense b x b complex product = 8 b^3; an ELL product of width K = 8 b^2 K.
     """
     N, b = p.device.n_rings, p.device.b
-    K = ell_width(p.device)
     n_c, n_r = p.grid.n_c, p.grid.n_r
-    inv, mul, ell = 8.0 * b ** 3, 8.0 * b ** 3, 8.0 * b * b * K
-    # recursions: N-1 steps of (inverse + 2 ELL products) per chain, plus the final
-    # inverse on real-axis chains; two chains per node
-    recur = 2 * (n_c + n_r) * (N - 1) * (inv + 2 * ell) + 2 * n_r * inv
+    inv, mul = 8.0 * b ** 3, 8.0 * b ** 3
+    # recursions: one dense inverse per ring step (the sparse coupling products are
+    # not counted), N-1 steps per chain plus the final inverse on real-axis chains;
+    # two chains per node
+    recur = 2 * (n_c + n_r) * (N - 1) * inv + 2 * n_r * inv
     cdiag = n_c * N * inv
     # lead columns: per ring one propagation product and one W Gamma product (+ b^2 dots)
     column = 2 * n_r * (N * (mul + 8.0 * b * b) + (N - 1) * mul)
@@ -98,19 +98,40 @@ def algorithmic_flops(p: W.Problem, decim_iters: np.ndarray) -> dict:
     return {"recur": recur, "cdiag": cdiag, "column": column, "decimate": dec}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p: W.Problem, n_c: int = 16, n_r: int = 48, seed: int = 99) -> dict:
-    """The oracle as it stands, timed on the host cores over a fixed sample of nodes."""
+    """The oracle as it stands, timed on the host cores over a fixed sample of nodes,
+    and in one thread on a smaller sample."""
     from concurrent.futures import ProcessPoolExecutor
     cores = min(os.cpu_count() or 1, 16, n_c + n_r)
     sub = W.subsample_grid(p.grid, n_c, n_r, seed)
     jobs = [("c", z) for z in sub.z_c] + [("r", E) for E in sub.E_r]
+    one = W.subsample_grid(p.grid, 2, 6, seed + 1)
+    t0 = time.perf_counter()
+    for kind, x in [("c", z) for z in one.z_c] + [("r", E) for E in one.E_r]:
+        _oracle_point((p, kind, x))
+    dt1 = time.perf_counter() - t0
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=cores) as ex:
         list(ex.map(_oracle_point, [(p, kind, x) for kind, x in jobs]))
     dt = time.perf_counter() - t0
     return {"value": len(jobs) / dt, "unit": "energy-point solves/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "one_thread": {"value": (one.n_c + one.n_r) / dt1, "unit": "energy-point solves/s",
+                           "sample": f"{one.n_c} contour + {one.n_r} real-axis nodes (seed {seed + 1}), "
+                                     f"{dt1:.2f} s"},
             "sample": f"{sub.n_c} contour + {sub.n_r} real-axis nodes of the same workload (seed {seed}), "
-                      f"numpy/LAPACK oracle incl. decimation, one process per core, {dt:.2f} s wall"}
+                      f"numpy/LAPACK oracle incl. decimation, one process per core (one BLAS thread each), "
+                      f"{dt:.2f} s wall"}
 
 
 def _oracle_point(args):
@@ -157,7 +178,8 @@ def run(p: W.Problem, precision: int, steps: int, warmup: int):
     # one detailed host solve for the decimation step counts (not timed)
     res = d.solve(p.bias, p.grid, details=True)
     out = dict(ms_per_step=1e3 * dt / steps, times=times, iters=res.decim_iters,
-               charge=charge.cpu().numpy(), current=float(cur.item()))
+               charge=charge.cpu().numpy(), current=float(cur.item()), T=T.cpu().numpy()[:g.n_r],
+               fp64_nodes=res.fp64_nodes)
     d.close()
     return out
 
@@ -203,7 +225,9 @@ def run_batch(ps, precision: int, steps: int, warmup: int, grid_scale: int = 0, 
     schedule = None
     if autotune:
         best = ws.autotune(jobs, stream, reps=1)
-        schedule = {"grid_scale": best.grid_scale, "order": best.order, "ms_per_solve": round(best.ms_per_solve, 2)}
+        schedule = {"grid_scale": best.grid_scale, "order": best.order, "ms_per_solve": round(best.ms_per_solve, 2),
+                    "chains_per_wave": {b: int(best.chains_per_wave[b]) for b in range(1, 25)
+                                        if best.chains_per_wave[b]}}
         log(f"  autotuned schedule {schedule}")
     for _ in range(warmup):
         ws.solve_dev(jobs, stream)
@@ -347,18 +371,57 @@ def measured_traffic(kernel: str, b: int, precision: str):
     or None when the kernel source changed since the counters were taken."""
     import glob
     import hashlib
-    if precision != "f64":
-        return None
+    t = "double" if precision == "f64" else "float"
     src = os.path.join(ROOT, "paper_2407_14633_amd", "csrc", "negf_kernels.hpp")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    names = {"recur": f"negf::k_recur<double, {b}>", "cdiag": f"negf::k_cdiag<double, {b}>",
-             "column": f"negf::k_column<double, {b}>", "decimate": f"negf::k_decimate_circ<{b}>"}
+    names = {"recur": f"negf::k_recur<{t}, {b}>", "cdiag": f"negf::k_cdiag<{t}, {b}>",
+             "column": f"negf::k_column<{t}, {b}>", "decimate": f"negf::k_decimate_circ<{b}>"}
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md")):
         for line in open(path):
             if line.startswith("machine-readable: "):
                 d = json.loads(line[len("machine-readable: "):])
                 if d.get("source_hash") == h and names.get(kernel) in d.get("hbm_bytes", {}):
                     return d["hbm_bytes"][names[kernel]]
+    return None
+
+
+def golden_reference(p: W.Problem):
+    """The oracle's stored full-grid result for this workload (written by
+    tests/golden/make_device_reference.py), if there is one."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{p.name}.npz")
+    if not os.path.exists(path):
+        return None
+    d = np.load(path)
+    return {"charge": d["charge"], "T": d["T"], "current": float(d["current"][0]), "file": os.path.relpath(path, ROOT)}
+
+
+def errors_vs(ref, r) -> dict:
+    """Charge (relative to max_i |charge_i|), current, and T(E) (relative to max_E T) against the oracle."""
+    if ref is None:
+        return None
+    q, T = ref["charge"], ref["T"]
+    return {"charge_rel": float(np.max(np.abs(r["charge"] - q)) / np.max(np.abs(q))),
+            "current_rel": abs(r["current"] - ref["current"]) / abs(ref["current"]),
+            "T_rel_to_max": float(np.max(np.abs(r["T"] - T)) / np.max(np.abs(T))),
+            "oracle_file": ref["file"]}
+
+
+def counted_flops(kernel: str, b: int, precision: str):
+    """FLOPs per dispatch of `kernel` counted by rocprofv3's VALU instruction counters
+    (committed summary), or None when the kernel source changed since."""
+    import glob
+    import hashlib
+    t = "double" if precision == "f64" else "float"
+    src = os.path.join(ROOT, "paper_2407_14633_amd", "csrc", "negf_kernels.hpp")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    name = {"recur": f"negf::k_recur<{t}, {b}>", "cdiag": f"negf::k_cdiag<{t}, {b}>",
+            "column": f"negf::k_column<{t}, {b}>"}.get(kernel)
+    for path in glob.glob(os.path.join(ROOT, "profiles", "valu_flops_*.md")):
+        for line in open(path):
+            if line.startswith("machine-readable: "):
+                d = json.loads(line[len("machine-readable: "):])
+                if d.get("source_hash") == h and name in d.get("counted_flops_per_dispatch", {}):
+                    return d["counted_flops_per_dispatch"][name]
     return None
 
 
@@ -372,9 +435,14 @@ def roofline(p, r, peak_tflops, precision="f64"):
                 best = (k, avg)
     k, avg = best
     ach = flops[k] / (avg * 1e-3) / 1e12
+    cnt = counted_flops(k, p.device.b, precision)
     return {"kernel": k, "bound": "alu", "achieved": round(ach, 4), "peak": peak_tflops, "unit": "TFLOP/s",
             "frac": round(ach / peak_tflops, 5), "traffic": measured_traffic(k, p.device.b, precision),
-            "avg_ms": round(avg, 4), "flops_per_launch": flops[k]}
+            "avg_ms": round(avg, 4), "flops_per_launch": flops[k],
+            "counted": None if cnt is None else {
+                "flops_per_launch": cnt, "achieved": round(cnt / (avg * 1e-3) / 1e12, 4),
+                "frac": round(cnt / (avg * 1e-3) / 1e12 / peak_tflops, 5),
+                "source": "rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64/F32 + MFMA_MOPS, all lanes"}}
 
 
 def main():
@@ -425,6 +493,7 @@ def main():
     log("fp64 ms/step", r64["ms_per_step"], "kernels", r64["times"])
     rf64 = roofline(p, r64, FP64_PEAK_TFLOPS)
     log("fp64 roofline", rf64)
+    golden = golden_reference(p)
     fp32 = None
     if not a.no_fp32:
         r32 = run(p, negf.FP32_BULK, a.steps, a.warmup)
@@ -432,14 +501,18 @@ def main():
         rf32 = roofline(p, r32, FP32_PEAK_TFLOPS, "f32")
         err = float(np.max(np.abs(r32["charge"] - r64["charge"])) / np.max(np.abs(r64["charge"])))
         fp32 = {"value": n_e / (r32["ms_per_step"] * 1e-3), "ms_per_step": r32["ms_per_step"],
+                "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
                 "roofline": rf32, "charge_rel_diff_vs_fp64": err,
-                "current_rel_diff_vs_fp64": abs(r32["current"] - r64["current"]) / abs(r64["current"] or 1.0)}
+                "current_rel_diff_vs_fp64": abs(r32["current"] - r64["current"]) / abs(r64["current"] or 1.0),
+                "real_nodes_recomputed_fp64": r32["fp64_nodes"], "real_nodes": p.grid.n_r,
+                "vs_oracle": errors_vs(golden, r32)}
     serving = None
     if not a.no_serving:
         serving = run_serving(a.requests, a.rate)
         log("serving", serving)
     line = {
         "metric": METRIC, "value": n_e / (r64["ms_per_step"] * 1e-3), "unit": "energy-point solves/s",
+        "fp64_vs_oracle": errors_vs(golden, r64),
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": r64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{p.name}: zigzag (17,0) CNT tight binding, {p.device.n_rings} rings, "

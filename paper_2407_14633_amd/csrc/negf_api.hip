@@ -47,7 +47,7 @@ bool finite_c(const negf_c64* p, size_t n) {
     return true;
 }
 
-const char* const kKernelNames[KT_COUNT] = {"decimate", "recur", "cdiag", "column", "reduce"};
+const char* const kKernelNames[KT_COUNT] = {"decimate", "recur", "cdiag", "column", "reduce", "fp64_recompute"};
 
 
 negf_status dalloc_raw(size_t* counter, void** p, size_t bytes) {
@@ -571,7 +571,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         const int B = groups[gi].L->B;
         double elems = 0.0;
         long long nreal = 0;
-        Launch LL{negf::KIND_COUNT, KT_COLUMN, gi, spans.size(), nfirsts.size(), (int)gcol[gi].size(), 1, 0, 0, 0, 1,
+        Launch LL{negf::KIND_COUNT, KT_FP64, gi, spans.size(), nfirsts.size(), (int)gcol[gi].size(), 1, 0, 0, 0, 1,
                   (long long)gall[gi], 1};
         for (const auto& x : gcol[gi]) {
             nfirsts.push_back((int)nreal);
@@ -586,11 +586,11 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         const long long per = (long long)(store_need / 16) - (long long)(node64_max / 16);   // fill guaranteed per round
         const int rounds = 1 + (int)std::ceil(frac * elems / (double)std::max<long long>(per, 1));
         for (int r = 0; r < rounds; ++r) {
-            launches.push_back(Launch{negf::KIND_COUNT, KT_COLUMN, gi, 0, 0, (int)nreal, 1, 0, nreal, 0, 3,
+            launches.push_back(Launch{negf::KIND_COUNT, KT_FP64, gi, 0, 0, (int)nreal, 1, 0, nreal, 0, 3,
                                       r == rounds - 1 ? -cap64 : cap64, 1});
             launches.push_back(
-                Launch{negf::KIND_RECUR64, KT_RECUR, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0, 1});
-            launches.push_back(Launch{negf::KIND_COLUMN64, KT_COLUMN, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0, 1});
+                Launch{negf::KIND_RECUR64, KT_FP64, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0, 1});
+            launches.push_back(Launch{negf::KIND_COLUMN64, KT_FP64, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0, 1});
         }
     }
     TRY(grow(w, w->scratch, scratch_need));

@@ -32,7 +32,7 @@ const negf::Launchers* launchers_for(int b);
 
 bool finite_c(const negf_c64* p, size_t n);
 
-enum { KT_DECIMATE = 0, KT_RECUR, KT_CDIAG, KT_COLUMN, KT_REDUCE, KT_COUNT };
+enum { KT_DECIMATE = 0, KT_RECUR, KT_CDIAG, KT_COLUMN, KT_REDUCE, KT_FP64, KT_COUNT };
 
 // Device flag slots per job: status bits of any node, first bad node, nodes
 // recomputed in FP64 (FP32-bulk form), unused.

@@ -30,16 +30,17 @@ def test_circulant_detection():
 
 
 def test_flop_model_counts():
-    """Recursion flops: 2 chains per node of (N-1) steps of (inverse + 2 ELL products), plus
-    the final inverse of the real-axis chains; with b, K, N small enough to count by hand."""
+    """Recursion flops: 2 chains per node of (N-1) dense inverses (8 b^3 each; the sparse
+    coupling products are not counted), plus the final inverse of the real-axis chains;
+    with b, K, N small enough to count by hand."""
     p = W.small_problem()
     N, b = p.device.n_rings, p.device.b
     K = bench.ell_width(p.device)
     assert K == 2                                     # zigzag couplings t(I + S^T) and tI
     f = bench.algorithmic_flops(p, np.full((p.grid.n_c + p.grid.n_r, 2), 10))
-    inv, ell = 8.0 * b ** 3, 8.0 * b * b * K
+    inv = 8.0 * b ** 3
     n_c, n_r = p.grid.n_c, p.grid.n_r
-    assert f["recur"] == 2 * (n_c + n_r) * (N - 1) * (inv + 2 * ell) + 2 * n_r * inv
+    assert f["recur"] == 2 * (n_c + n_r) * (N - 1) * inv + 2 * n_r * inv
     assert f["cdiag"] == n_c * N * inv
     # ring-mode decimation: 115 b flops per two-ring doubling step and mode, + per-node finish
     nodes = n_c + n_r
