@@ -375,19 +375,23 @@ void negf_modes_destroy(negf_modes *m);
 
 /* ------------------------------------------------------------ serving ----
  * Self-consistent bias points (Section 2.3, Algorithm 3) served with continuous
- * batching.  A request is a device with flat leads, a bias point and a fixed
- * energy grid.  The server iterates
+ * batching.  A request is a device with flat leads, a bias point and an energy
+ * grid (fixed, or semi-adaptive and rebuilt as the potential moves).  The server
+ * iterates
  *     rho_in -> Poisson -> U -> NEGF (batched with every running request) -> rho_out
  *     -> Broyden's modified second method on rho (per-ring electron counts)
- * until max_j |rho_in_j - rho_out_j| / (rho_in_j + rho_out_j) < tol, starting from
+ * until the stopping norm (request field norm) falls below tol, starting from
  * rho_in = n_ref.  Electrostatics: per ring j, potential phi_j (V),
  *     -(eps_1d/dz^2)(phi_{j+1} - 2 phi_j + phi_{j-1}) + c_gate (phi_j - V_GS)
  *         = -e (rho_j - n_ref_j)/dz,   phi_{-1} = 0 (source), phi_N = V_DS (drain),
  * and the electron potential energy U_j = -phi_j eV on every atom of ring j.  The
  * source lead sits at U = 0 and level mu_S, the drain lead at U = -V_DS and level
  * mu_S - V_DS, both at temperature kT.  Lead self-energies are decimated once per
- * request and reused on every pass.  A request's results do not depend on the
- * other requests that share its passes.
+ * grid and reused on every pass until the grid is rebuilt.  Since U is uniform on
+ * each ring, a ring-circulant tube (every zigzag tube) runs in mode space by
+ * default: b scalar chains per energy, exact, at O(b N) instead of O(b^3 N) per
+ * node.  A request's results do not depend on the other requests that share its
+ * passes.
  *
  * Admission: first come first served while the estimated HBM footprint of the
  * running requests fits hbm_budget minus the two recursion stores
@@ -412,6 +416,25 @@ typedef struct {
     const double *n_ref;                  /* [n_rings] electrons per ring when neutral  */
     double zeta, tol;                     /* Broyden fraction; stopping norm            */
     int history, max_iter;                /* stored Broyden columns (<= 32); pass limit */
+    int basis;              /* 0: mode space (Section 2.2.2, exact: every mode kept) when every
+                               device and lead block is ring-circulant, else real space;
+                               1: real space always                                          */
+    int norm;               /* stopping norm compared with tol:
+                               0: max_j |rho_in_j - rho_out_j| / (rho_in_j + rho_out_j)
+                                  (Algorithm 3);
+                               1: max_j |phi(rho_out)_j - phi(rho_in)_j| in eV (per electron),
+                                  the change of the potential that the output charge implies
+                                  (the linear Poisson operator with zero boundary values on
+                                  rho_in - rho_out)                                         */
+    double grid_density[3]; /* all 0: the fixed real-axis grid E_r/w_r.  All > 0: the
+                               semi-adaptive grid (Section 3.3; see negf_semi_adaptive_grid)
+                               with these densities (nodes per kT) in its three parts,
+                               rebuilt at the request's current potential before NEGF pass
+                               1, 1 + grid_refresh, 1 + 2 grid_refresh, ...; E_r/w_r and n_r
+                               are then ignored                                              */
+    double grid_l1, grid_l2;  /* guessed part limits of every rebuild (eV)                  */
+    double grid_a, grid_b;    /* refinement E_l1 - a kT, E_s + b kT (the paper: 3, 1)       */
+    int grid_refresh;         /* passes between rebuilds; 0 = 50                            */
 } negf_sc_request;
 
 typedef struct {
@@ -421,6 +444,8 @@ typedef struct {
     double eps_max;      /* stopping norm of the last pass                                 */
     double current;      /* A, at the last potential                                       */
     double t_queue_ms, t_run_ms, t_total_ms;   /* submit->admit, admit->done, submit->done */
+    int n_r;             /* real-axis nodes of the last pass                               */
+    int mode_space;      /* 1: the request ran as b scalar mode chains                     */
 } negf_sc_result;
 
 typedef struct {

@@ -18,8 +18,17 @@ reduced to one dimension along the tube axis):
   runs while eps_max >= tol; the printed "eta" of the W update is the Broyden
   fraction zeta; a history of H stored columns restarts the method (m <- 0)
   once m would exceed H.
+* ``potential_residual``: phi(rho_out) - phi(rho_in), the change of the
+  electrostatic potential that the output charge implies; by linearity it solves
+  the Poisson operator with zero boundary values and right-hand side e f / dz.
+  Its maximum (V, i.e. eV for one electron) is the alternative stopping norm
+  (norm = 1) that states the tolerance as a potential.
 * ``self_consistent``: the loop rho_in -> Poisson -> U -> NEGF (the FP64
-  oracle of ``negf_oracle``) -> rho_out -> Broyden, from rho_in = n_ref.
+  oracle of ``negf_oracle``) -> rho_out -> Broyden, from rho_in = n_ref.  With
+  a semi-adaptive grid (Section 3.3), the real-axis nodes are rebuilt by
+  ``grid_oracle.semi_adaptive_grid`` at the current potential before NEGF pass
+  1, 1 + refresh, 1 + 2 refresh, ... (reading: "refreshed every so many
+  iterations" counts NEGF passes, the first rebuild before the first solve).
 
 Pins: ``tests/test_sc_oracle_pins.py``.
 """
@@ -46,6 +55,19 @@ def poisson_rings(rho, elec):
     rhs[0] += k * 0.0                         # source: phi_{-1} = 0
     rhs[-1] += k * elec.V_DS                  # drain:  phi_N = V_DS
     return solve_banded((1, 1), ab, rhs)
+
+
+def potential_residual(f, elec):
+    """phi(rho_in - f) - phi(rho_in) for f = rho_in - rho_out: the tridiagonal Poisson
+    operator of ``poisson_rings`` with zero boundary values applied to e f / dz."""
+    f = np.asarray(f, np.float64)
+    N = f.shape[0]
+    k = elec.eps_1d / elec.dz ** 2
+    ab = np.zeros((3, N))
+    ab[0, 1:] = -k
+    ab[1, :] = 2.0 * k + elec.c_gate
+    ab[2, :-1] = -k
+    return solve_banded((1, 1), ab, E_CHARGE * f / elec.dz)
 
 
 def ring_potential(phi, b):
@@ -111,22 +133,33 @@ def negf_problem(req, U):
 
 def self_consistent(req, solve=None):
     """Runs the loop from rho_in = n_ref.  Returns dict(U, phi, rho, charge, current,
-    iterations, eps_max, converged, history of eps_max)."""
+    iterations, eps_max, converged, history of eps_max, n_r of the last grid)."""
+    from dataclasses import replace
+
+    from . import grid_oracle as G
     solve = solve or (lambda p: O.solve(p))
     b = req.device.b
     br = Broyden(req.elec.n_ref, req.zeta, req.history)
     trace = []
     out = None
+    grid = req.grid
     for it in range(1, req.max_iter + 1):
         phi = poisson_rings(br.rho_in, req.elec)                # step 1: electrostatics
         U = ring_potential(phi, b)
-        res = solve(negf_problem(req, U))                       # step 1: NEGF
+        if req.grid_density is not None and (it - 1) % (req.grid_refresh or 50) == 0:
+            probe = negf_problem(req, U)
+            E_r, w_r, _ = G.semi_adaptive_grid(probe, req.grid_limits[0], req.grid_limits[1], req.grid_a,
+                                               req.grid_b, req.grid_density)
+            grid = type(req.grid)(req.grid.z_c, req.grid.w_c, E_r, w_r)
+        res = solve(negf_problem(replace(req, grid=grid), U))   # step 1: NEGF
         rho_out = ring_counts(res["charge"], b)
         eps_max, f, df, d = br.step(rho_out)
+        if req.norm == 1:
+            eps_max = float(np.max(np.abs(potential_residual(f, req.elec))))
         trace.append(eps_max)
         out = dict(U=U, phi=phi, rho=rho_out, rho_in=br.rho_in.copy(), charge=res["charge"],
                    current=res["current"], iterations=it, eps_max=eps_max, converged=eps_max < req.tol,
-                   trace=trace)
+                   trace=trace, n_r=grid.n_r)
         if eps_max < req.tol:
             break
         br.update(f, df, d)

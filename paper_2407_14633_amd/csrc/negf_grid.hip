@@ -56,8 +56,14 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
     if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
-void three_parts(double E_min, double E_max, double l1, double l2, const double* dens, double kT,
-                 std::vector<double>& E, std::vector<double>& W) {
+double clip(double v, double lo, double hi) { return std::min(std::max(v, lo), hi); }
+
+}  // namespace
+
+namespace negf_host {
+
+void grid_parts(double E_min, double E_max, double l1, double l2, const double* dens, double kT,
+                std::vector<double>& E, std::vector<double>& W) {
     E.clear();
     W.clear();
     const double lo[3] = {E_min, l1, l2}, hi[3] = {l1, l2, E_max};
@@ -73,7 +79,7 @@ void three_parts(double E_min, double E_max, double l1, double l2, const double*
     }
 }
 
-double fermi(double E, double mu, double kT) {
+double host_fermi(double E, double mu, double kT) {
     const double x = (E - mu) / kT;
     if (x > 0) {
         const double e = std::exp(-x);
@@ -82,9 +88,30 @@ double fermi(double E, double mu, double kT) {
     return 1.0 / (1.0 + std::exp(x));
 }
 
-double clip(double v, double lo, double hi) { return std::min(std::max(v, lo), hi); }
+void grid_window(const negf_bias& bias, double* E_min, double* E_max, double* kT) {
+    const double tail = 14.0;
+    *kT = std::min(bias.kT_L, bias.kT_R);
+    *E_min = std::min(bias.mu_L, bias.mu_R) - tail * std::min(bias.kT_L, bias.kT_R);
+    *E_max = std::max(bias.mu_L, bias.mu_R) + tail * std::max(bias.kT_L, bias.kT_R);
+}
 
-}  // namespace
+void grid_refine(const negf_bias& bias, const std::vector<double>& Ep, const std::vector<double>& integrand,
+                 double l1, double a, double b, double* n1, double* n2, double* Es) {
+    double E_min, E_max, kT;
+    grid_window(bias, &E_min, &E_max, &kT);
+    int best = 0;
+    double fbest = -1.0;
+    for (size_t k = 0; k < Ep.size(); ++k)
+        if (integrand[k] > fbest) {
+            fbest = integrand[k];
+            best = (int)k;
+        }
+    *Es = Ep.empty() ? E_min : Ep[best];
+    *n1 = clip(clip(l1, E_min, E_max) - a * kT, E_min, E_max);
+    *n2 = clip(*Es + b * kT, *n1, E_max);
+}
+
+}  // namespace negf_host
 
 extern "C" negf_status negf_semi_adaptive_grid(negf_device* d, const negf_bias* bias, double E_l1, double E_l2,
                                                double a, double b, const double* density, double* E_r, double* w_r,
@@ -95,13 +122,11 @@ extern "C" negf_status negf_semi_adaptive_grid(negf_device* d, const negf_bias* 
         if (!(density[p] > 0) || density[p] > 1e6) return fail(NEGF_EINVAL, "density[%d] out of range", p);
     if (!std::isfinite(E_l1) || !std::isfinite(E_l2) || !std::isfinite(a) || !std::isfinite(b))
         return fail(NEGF_EINVAL, "limits not finite");
-    const double tail = 14.0;
-    const double kT = std::min(bias->kT_L, bias->kT_R);
-    const double E_min = std::min(bias->mu_L, bias->mu_R) - tail * std::min(bias->kT_L, bias->kT_R);
-    const double E_max = std::max(bias->mu_L, bias->mu_R) + tail * std::max(bias->kT_L, bias->kT_R);
+    double E_min, E_max, kT;
+    grid_window(*bias, &E_min, &E_max, &kT);
     const double l1 = clip(E_l1, E_min, E_max), l2 = clip(E_l2, E_min, E_max);
     std::vector<double> Ep, Wp;
-    three_parts(E_min, E_max, l1, l2, density, kT, Ep, Wp);
+    grid_parts(E_min, E_max, l1, l2, density, kT, Ep, Wp);
     const int np = (int)Ep.size();
     if (np > (1 << 22)) return fail(NEGF_EINVAL, "probe grid of %d nodes", np);
     // probe: A_L, A_R on the grid of the guessed limits
@@ -113,25 +138,20 @@ extern "C" negf_status negf_semi_adaptive_grid(negf_device* d, const negf_bias* 
     o.ar_diag = AR.data();
     TRY(negf_solve_ex(d, bias, 0, nullptr, nullptr, np, Ep.data(), Wp.data(), &o));
     const int jc = N / 2;
-    int best = 0;
-    double fbest = -1.0;
+    std::vector<double> g(np);
     for (int k = 0; k < np; ++k) {
-        const double fl = fermi(Ep[k], bias->mu_L, bias->kT_L), fr = fermi(Ep[k], bias->mu_R, bias->kT_R);
+        const double fl = host_fermi(Ep[k], bias->mu_L, bias->kT_L), fr = host_fermi(Ep[k], bias->mu_R, bias->kT_R);
         double acc = 0.0;
         for (int i = 0; i < B; ++i) {
             const size_t q = (size_t)k * N * B + (size_t)jc * B + i;
             acc += fl * AL[q] + fr * AR[q];
         }
-        if (acc > fbest) {
-            fbest = acc;
-            best = k;
-        }
+        g[k] = acc;
     }
-    const double Es = Ep[best];
-    const double n1 = clip(l1 - a * kT, E_min, E_max);
-    const double n2 = clip(Es + b * kT, n1, E_max);
+    double n1, n2, Es;
+    grid_refine(*bias, Ep, g, l1, a, b, &n1, &n2, &Es);
     std::vector<double> Ef, Wf;
-    three_parts(E_min, E_max, n1, n2, density, kT, Ef, Wf);
+    grid_parts(E_min, E_max, n1, n2, density, kT, Ef, Wf);
     *n_r = (int)Ef.size();
     if (limits) {
         limits[0] = n1;

@@ -134,4 +134,26 @@ negf_status finish(negf_workspace* w, int* failed_job);
 negf_status ws_create(negf_workspace** out, size_t store_bytes);
 void ws_destroy(negf_workspace* w);
 
+// Ring-circulant test of a b x b block: M[i][j] == M[0][(j - i) mod b], exactly.
+bool ring_circulant(const negf_c64* M, int b);
+
+// Semi-adaptive real-axis grid (Section 3.3).  grid_window: [E_min, E_max] of
+// Eq. 4 and kT_min.  grid_parts: Gauss-Legendre nodes/weights on the three parts
+// split at l1 <= l2, density[p] nodes per kT (at least one per non-empty part).
+// grid_refine: peak E_s of the probe integrand on the grid of the guessed limits
+// (first maximum), refined limits {l1 - a kT, E_s + b kT} clipped to the window.
+void grid_window(const negf_bias& bias, double* E_min, double* E_max, double* kT);
+void grid_parts(double E_min, double E_max, double l1, double l2, const double* density, double kT,
+                std::vector<double>& E, std::vector<double>& W);
+void grid_refine(const negf_bias& bias, const std::vector<double>& Ep, const std::vector<double>& integrand,
+                 double l1, double a, double b, double* n1, double* n2, double* Es);
+double host_fermi(double E, double mu, double kT);
+
 }  // namespace negf_host
+
+// A tube in mode space: one scalar chain (ring size 1) per kept ring mode.
+struct negf_modes {
+    int N = 0, b = 0;
+    std::vector<int> modes;
+    std::vector<negf_device*> devs;
+};

@@ -21,22 +21,7 @@
 
 using namespace negf_host;
 
-struct negf_modes {
-    int N = 0, b = 0;
-    std::vector<int> modes;
-    std::vector<negf_device*> devs;   // one scalar chain per kept mode
-};
-
 namespace {
-
-bool circulant(const negf_c64* M, int b) {
-    for (int i = 0; i < b; ++i)
-        for (int j = 0; j < b; ++j) {
-            const negf_c64 a = M[(size_t)i * b + j], c = M[(size_t)((j - i + b) % b)];
-            if (a.re != c.re || a.im != c.im) return false;
-        }
-    return true;
-}
 
 negf_c64 mode_value(const negf_c64* M, int b, int q) {
     std::complex<double> acc(0.0, 0.0);
@@ -49,6 +34,15 @@ negf_c64 mode_value(const negf_c64* M, int b, int q) {
 }
 
 }  // namespace
+
+bool negf_host::ring_circulant(const negf_c64* M, int b) {
+    for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+            const negf_c64 a = M[(size_t)i * b + j], c = M[(size_t)((j - i + b) % b)];
+            if (a.re != c.re || a.im != c.im) return false;
+        }
+    return true;
+}
 
 extern "C" {
 
@@ -68,18 +62,18 @@ negf_status negf_modes_create(negf_modes** out, int n_rings, int b, const negf_c
     if (n_modes < 0 || n_modes > b || (n_modes > 0 && !modes)) return fail(NEGF_EINVAL, "bad mode list");
     const size_t b2 = (size_t)b * b;
     for (int j = 0; j < n_rings; ++j)
-        if (!circulant(h_diag + j * b2, b)) return fail(NEGF_EINVAL, "h_diag[%d] is not circulant", j);
+        if (!ring_circulant(h_diag + j * b2, b)) return fail(NEGF_EINVAL, "h_diag[%d] is not circulant", j);
     for (int j = 0; j + 1 < n_rings; ++j)
-        if (!circulant(h_up + j * b2, b)) return fail(NEGF_EINVAL, "h_up[%d] is not circulant", j);
+        if (!ring_circulant(h_up + j * b2, b)) return fail(NEGF_EINVAL, "h_up[%d] is not circulant", j);
     const negf_lead* ls[2] = {left, right};
     for (int l = 0; l < 2; ++l) {
         const negf_lead* L = ls[l];
         if (L->period < 1 || L->period > NEGF_MAX_PERIOD || !L->h_diag || !L->h_up || !L->tau)
             return fail(NEGF_EINVAL, "bad lead %d", l);
         for (int r = 0; r < L->period; ++r)
-            if (!circulant(L->h_diag + r * b2, b) || !circulant(L->h_up + r * b2, b))
+            if (!ring_circulant(L->h_diag + r * b2, b) || !ring_circulant(L->h_up + r * b2, b))
                 return fail(NEGF_EINVAL, "lead %d blocks are not circulant", l);
-        if (!circulant(L->tau, b)) return fail(NEGF_EINVAL, "lead %d coupling is not circulant", l);
+        if (!ring_circulant(L->tau, b)) return fail(NEGF_EINVAL, "lead %d coupling is not circulant", l);
     }
     negf_modes* m = new negf_modes();
     m->N = n_rings;

@@ -6,6 +6,15 @@
 //     a (2 phi_j - phi_{j-1} - phi_{j+1}) + phi_j = V_GS - c (rho_in_j - n_ref_j)
 //     a = eps_1d / (c_gate dz^2),  c = e / (c_gate dz),  phi_{-1} = 0,  phi_N = V_DS
 //   U_{j,i} = -phi_j (eV) written into the device's potential.
+// Stopping norm: the relative charge change max_j |f_j| / (rho_in_j + rho_out_j)
+// of Algorithm 3, or the potential residual max_j |phi(rho_out)_j - phi(rho_in)_j|
+// (eV for one electron), which the linear Poisson operator gives as the solution
+// delta of  a (2 delta_j - delta_{j-1} - delta_{j+1}) + delta_j = c f_j  with
+// delta_{-1} = delta_N = 0.
+// The per-ring charge is a strided sum over the NEGF output (the atoms of a ring
+// in real space, the ring's mode chains in mode space), and the new potential is
+// written to every array that the request's NEGF step reads (one real-space
+// device, or one scalar chain per mode).
 // Reductions run in a fixed order inside the workgroup, so a request's
 // iterates do not depend on which other requests share the launch.
 #pragma once
@@ -17,12 +26,15 @@ constexpr int SC_THREADS = 256;
 constexpr int SC_MAX_HISTORY = 32;
 
 struct ScReq {
-    int N, b, H, max_iter;
+    int N, H, max_iter;
+    int norm;                 // 0: relative charge change; 1: potential residual (eV)
+    int n_part, q_ring, q_part;   // rho_out_j = sum_{i < n_part} charge[j q_ring + i q_part]
+    int n_U, U_w;             // potential arrays written, entries per ring in each
     double zeta, tol;
     double a, c;              // Poisson coefficients (see above)
     double V_GS, V_DS;
-    const double* charge;     // [N*b] NEGF output of this pass
-    double* U;                // [N*b] device potential (written)
+    const double* charge;     // NEGF output of this pass
+    double* const* U;         // [n_U] device potentials, each [N * U_w] (written)
     const double* n_ref;      // [N]
     double* rho_in;           // [N]
     double* rho_in_old;       // [N]
@@ -30,7 +42,7 @@ struct ScReq {
     double* s;                // [N]
     double* Vt;               // [H+1][N] rows 1..H of V^T
     double* Wc;               // [H+1][N] columns 1..H of W
-    double* work;             // [3N]
+    double* work;             // [4N]
     int* stat;                // [4]: m, passes, state (0 running, 1 converged, 2 pass limit)
     double* diag;             // [2]: eps_max of the last pass, |Delta f|^2
 };
@@ -47,13 +59,16 @@ __device__ __forceinline__ double sc_block_sum(double v, double* red) {
     return red[0];
 }
 
+// maximum that keeps a NaN (fmax would drop it)
+__device__ __forceinline__ double nan_max(double x, double y) { return (x != x || y != y) ? x + y : fmax(x, y); }
+
 __device__ __forceinline__ double sc_block_max(double v, double* red) {
     const int t = threadIdx.x;
     __syncthreads();
     red[t] = v;
     __syncthreads();
     for (int w = SC_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] = fmax(red[t], red[t + w]);
+        if (t < w) red[t] = nan_max(red[t], red[t + w]);
         __syncthreads();
     }
     return red[0];
@@ -65,7 +80,8 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
     const ScReq& R = reqs[blockIdx.x];
     __shared__ double red[SC_THREADS];
     __shared__ double s_k[SC_MAX_HISTORY + 1];
-    const int t = threadIdx.x, N = R.N, b = R.b;
+    __shared__ double s_eps;
+    const int t = threadIdx.x, N = R.N;
     double* f = R.work;           // [N] f of this pass
     double* df = R.work + N;      // [N] Delta f
     if (mode == 0) {
@@ -87,17 +103,44 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
         double emax = 0.0, dsum = 0.0;
         for (int j = t; j < N; j += SC_THREADS) {
             double ro = 0.0;
-            for (int i = 0; i < b; ++i) ro += R.charge[(size_t)j * b + i];
+            for (int i = 0; i < R.n_part; ++i) ro += R.charge[(size_t)j * R.q_ring + (size_t)i * R.q_part];
             const double ri = R.rho_in[j];
             const double fj = ri - ro;
             const double dj = fj - R.f_old[j];
             f[j] = fj;
             df[j] = dj;
-            emax = fmax(emax, fabs(fj / (ri + ro)));
+            emax = nan_max(emax, fabs(fj / (ri + ro)));
             dsum += dj * dj;
         }
         emax = sc_block_max(emax, red);
         const double d = sc_block_sum(dsum, red);
+        if (R.norm == 1) {                 // potential residual: Thomas sweep with right-hand side c f
+            __syncthreads();
+            if (t == 0) {
+                double* cp = R.work + 2 * N;
+                double* dp = R.work + 3 * N;
+                const double a = R.a, dg = 2.0 * a + 1.0;
+                double cprev = 0.0, dprev = 0.0;
+                for (int j = 0; j < N; ++j) {
+                    const double den = dg + a * cprev;
+                    const double cj = -a / den;
+                    const double dj = (R.c * f[j] + a * dprev) / den;
+                    cp[j] = cj;
+                    dp[j] = dj;
+                    cprev = cj;
+                    dprev = dj;
+                }
+                double next = 0.0, m = 0.0;
+                for (int j = N - 1; j >= 0; --j) {
+                    const double v = dp[j] - (j + 1 < N ? cp[j] * next : 0.0);
+                    next = v;
+                    m = nan_max(m, fabs(v));
+                }
+                s_eps = m;
+            }
+            __syncthreads();
+            emax = s_eps;
+        }
         const int passes = R.stat[1] + 1;
         int m = R.stat[0];
         __syncthreads();
@@ -186,7 +229,11 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
         }
     }
     __syncthreads();
-    for (int q = t; q < N * b; q += SC_THREADS) R.U[q] = -phi[q / b];
+    for (int u = 0; u < R.n_U; ++u) {
+        double* Uu = R.U[u];
+        const int w = R.U_w;
+        for (int q = t; q < N * w; q += SC_THREADS) Uu[q] = -phi[q / w];
+    }
 }
 
 }  // namespace negf

@@ -52,14 +52,22 @@ struct ScJob {
     std::vector<negf_c64> z_c, w_c;
     std::vector<double> E_r, w_r, n_ref;
     double a = 0, c = 0, zeta = 0, tol = 0;
-    int H = 0, max_iter = 0;
+    int H = 0, max_iter = 0, norm = 0;
+    bool want_modes = false;      // every block ring-circulant and mode space not declined
+    // semi-adaptive real-axis grid, rebuilt before NEGF pass 1, 1 + refresh, ...
+    bool adaptive = false;
+    double density[3] = {0, 0, 0}, g_l1 = 0, g_l2 = 0, g_a = 0, g_b = 0;
+    int refresh = 50;
+    int n_r = 0, n_r_cap = 0;     // real-axis nodes now, and the capacity of their arrays
     size_t footprint = 0;
     // device state
-    negf_device* dev = nullptr;
+    negf_device* dev = nullptr;   // real space
+    negf_modes* modes = nullptr;  // mode space: one scalar chain per ring mode
     void* mem = nullptr;          // one allocation for grid, outputs, self-energies and mixing state
     negf_c64 *d_zc = nullptr, *d_wc = nullptr, *d_sigma = nullptr;
-    double *d_Er = nullptr, *d_wr = nullptr, *d_charge = nullptr, *d_T = nullptr, *d_cur = nullptr;
+    double *d_Er = nullptr, *d_wr = nullptr, *d_charge = nullptr, *d_cur = nullptr;
     double *d_nref = nullptr, *d_state = nullptr;
+    double** d_Uptr = nullptr;    // potentials that the self-consistency step writes
     bool sigma_ready = false;
     negf::ScReq rq{};
     // results
@@ -70,6 +78,10 @@ struct ScJob {
     bool done = false;
     std::vector<double> charge_out, U_out;
     std::vector<double> trace;    // stopping norm of every pass
+
+    int n_jobs() const { return modes ? (int)modes->devs.size() : 1; }
+    int ring_width() const { return modes ? 1 : b; }   // entries per ring of each NEGF job
+    size_t ne_cap() const { return z_c.size() + (size_t)n_r_cap; }
 };
 
 }  // namespace
@@ -85,6 +97,7 @@ struct negf_server {
     int* h_stat = nullptr;        // pinned copies
     double* h_diag = nullptr;
     negf::ScReq* d_reqs = nullptr;   // [max_inflight]
+    DBuf probe;                   // grid-probe nodes and throwaway outputs
     std::vector<int> free_slots;
     std::thread th;
     std::mutex mu;
@@ -101,17 +114,24 @@ struct negf_server {
 
 namespace {
 
+double clip(double v, double lo, double hi) { return std::min(std::max(v, lo), hi); }
+
 size_t estimate_footprint(const ScJob& j) {
-    const size_t Nb = (size_t)j.N * j.b, b2 = (size_t)j.b * j.b, ne = j.z_c.size() + j.E_r.size();
+    const size_t N = j.N, Nb = N * j.b, b2 = (size_t)j.b * j.b, nc = j.z_c.size(), nr = j.n_r_cap;
+    const size_t ne = nc + nr;
     const bool f32 = j.opt.precision == NEGF_FP32_BULK;
     size_t s = 0;
-    s += (size_t)j.N * b2 * 16 + Nb * 8 + 8192;                        // device Hamiltonian, potential, couplings
-    s += j.z_c.size() * 32 + j.E_r.size() * 16;                        // grid
-    s += Nb * 8 + j.E_r.size() * 8 + 8;                                // outputs
-    s += ne * 2 * b2 * 16;                                             // self-energy cache
-    s += (size_t)(8 + 2 * (j.H + 1)) * j.N * 8;                        // mixing state and Poisson scratch
-    s += j.z_c.size() * Nb * (f32 ? 8 : 16) + j.E_r.size() * 2 * Nb * (f32 ? 4 : 8);   // per-node diagonals
-    s += (size_t)32 * Nb * 8 + ne * 96;                                // reduction partials, per-node scalars
+    if (j.want_modes)
+        s += (size_t)j.b * (N * 64 + 8192);                            // b scalar chains
+    else
+        s += N * b2 * 16 + Nb * 8 + 8192;                              // device Hamiltonian, potential, couplings
+    s += nc * 32 + nr * 16;                                            // grid
+    s += Nb * 8 + (size_t)j.b * 16;                                    // outputs, potential pointers
+    s += ne * 2 * (j.want_modes ? (size_t)j.b : b2) * 16;              // self-energy cache
+    s += (size_t)(9 + 2 * (j.H + 1)) * N * 8;                          // mixing state and Poisson scratch
+    s += nc * Nb * (f32 ? 8 : 16) + nr * 2 * Nb * 8;                   // per-node diagonals
+    s += (size_t)32 * Nb * 8 + ne * (j.want_modes ? (size_t)j.b : 1) * 96;   // reduction partials, per-node scalars
+    if (j.adaptive) s += nr * 16 * (j.want_modes ? (size_t)j.b : 1);  // grid probe at the capacity
     return s;
 }
 
@@ -119,6 +139,8 @@ size_t estimate_footprint(const ScJob& j) {
 void release(ScJob* j) {
     if (j->dev) negf_destroy(j->dev);
     j->dev = nullptr;
+    if (j->modes) negf_modes_destroy(j->modes);
+    j->modes = nullptr;
     if (j->mem) (void)hipFree(j->mem);
     j->mem = nullptr;
 }
@@ -127,43 +149,60 @@ negf_status setup(negf_server* S, ScJob* j) {
     negf_lead leads[2];
     for (int l = 0; l < 2; ++l)
         leads[l] = negf_lead{j->lead_period[l], j->lead_hd[l].data(), j->lead_hu[l].data(), j->lead_tau[l].data()};
-    TRY(negf_create_device(&j->dev, j->N, j->b, j->h_diag.data(), j->N > 1 ? j->h_up.data() : nullptr, &leads[0],
-                           &leads[1], &j->opt));
-    std::vector<double> U0((size_t)j->N * j->b, 0.0);
-    TRY(negf_set_potential(j->dev, U0.data(), 0.0, -j->V_DS));
-    const size_t nc = j->z_c.size(), nr = j->E_r.size(), ne = nc + nr, N = j->N, Nb = N * j->b;
-    const size_t b2 = (size_t)j->b * j->b;
-    const size_t n_state = 5 * N + 2 * (size_t)(j->H + 1) * N + 3 * N;
-    // ten sub-arrays, each rounded up to 256 bytes
-    const size_t bytes = nc * 32 + ne * 2 * b2 * 16 + (2 * nr + Nb + std::max<size_t>(nr, 1) + 1 + N + n_state) * 8 +
-                         10 * 256;
+    const size_t N = j->N;
+    if (j->want_modes) {
+        TRY(negf_modes_create(&j->modes, j->N, j->b, j->h_diag.data(), j->N > 1 ? j->h_up.data() : nullptr,
+                              &leads[0], &leads[1], &j->opt, 0, nullptr));
+        std::vector<double> U0(N, 0.0);
+        TRY(negf_modes_set_potential(j->modes, U0.data(), 0.0, -j->V_DS));
+    } else {
+        TRY(negf_create_device(&j->dev, j->N, j->b, j->h_diag.data(), j->N > 1 ? j->h_up.data() : nullptr,
+                               &leads[0], &leads[1], &j->opt));
+        std::vector<double> U0(N * j->b, 0.0);
+        TRY(negf_set_potential(j->dev, U0.data(), 0.0, -j->V_DS));
+    }
+    const int nj = j->n_jobs();
+    const size_t nc = j->z_c.size(), nr = j->n_r_cap, ne = j->ne_cap(), Nb = N * j->b;
+    const size_t sig_per_node = j->modes ? (size_t)j->b : (size_t)j->b * j->b;   // 2 x this per node
+    const size_t n_state = 5 * N + 2 * (size_t)(j->H + 1) * N + 4 * N;
+    // eleven sub-arrays, each rounded up to 256 bytes
+    const size_t bytes = nc * 32 + ne * 2 * sig_per_node * 16 + (2 * nr + Nb + nj + N + n_state) * 8 + nj * 8 +
+                         11 * 256;
     HIPCHK(hipMalloc(&j->mem, bytes));
     char* p = static_cast<char*>(j->mem);
     auto take = [&](size_t n) { char* q = p; p += (n + 255) & ~size_t(255); return q; };
     j->d_zc = reinterpret_cast<negf_c64*>(take(nc * 16));
     j->d_wc = reinterpret_cast<negf_c64*>(take(nc * 16));
-    j->d_sigma = reinterpret_cast<negf_c64*>(take(ne * 2 * b2 * 16));
+    j->d_sigma = reinterpret_cast<negf_c64*>(take(ne * 2 * sig_per_node * 16));
     j->d_Er = reinterpret_cast<double*>(take(nr * 8));
     j->d_wr = reinterpret_cast<double*>(take(nr * 8));
     j->d_charge = reinterpret_cast<double*>(take(Nb * 8));
-    j->d_T = reinterpret_cast<double*>(take(std::max<size_t>(nr, 1) * 8));
-    j->d_cur = reinterpret_cast<double*>(take(8));
+    j->d_cur = reinterpret_cast<double*>(take(nj * 8));
     j->d_nref = reinterpret_cast<double*>(take(N * 8));
     j->d_state = reinterpret_cast<double*>(take(n_state * 8));
+    j->d_Uptr = reinterpret_cast<double**>(take(nj * 8));
     if (nc) {
         HIPCHK(hipMemcpy(j->d_zc, j->z_c.data(), nc * 16, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(j->d_wc, j->w_c.data(), nc * 16, hipMemcpyHostToDevice));
     }
-    if (nr) {
-        HIPCHK(hipMemcpy(j->d_Er, j->E_r.data(), nr * 8, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(j->d_wr, j->w_r.data(), nr * 8, hipMemcpyHostToDevice));
+    if (j->n_r) {
+        HIPCHK(hipMemcpy(j->d_Er, j->E_r.data(), (size_t)j->n_r * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(j->d_wr, j->w_r.data(), (size_t)j->n_r * 8, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemcpy(j->d_nref, j->n_ref.data(), N * 8, hipMemcpyHostToDevice));
+    std::vector<double*> uptr(nj);
+    for (int k = 0; k < nj; ++k) uptr[k] = j->modes ? j->modes->devs[k]->d_U : j->dev->d_U;
+    HIPCHK(hipMemcpy(j->d_Uptr, uptr.data(), nj * 8, hipMemcpyHostToDevice));
     negf::ScReq& R = j->rq;
     R.N = j->N;
-    R.b = j->b;
     R.H = j->H;
     R.max_iter = j->max_iter;
+    R.norm = j->norm;
+    R.n_part = j->b;
+    R.q_ring = j->modes ? 1 : j->b;                // real space: the ring's atoms are adjacent
+    R.q_part = j->modes ? j->N : 1;                // mode space: mode k's chain starts at k N
+    R.n_U = nj;
+    R.U_w = j->ring_width();
     R.zeta = j->zeta;
     R.tol = j->tol;
     R.a = j->a;
@@ -171,7 +210,7 @@ negf_status setup(negf_server* S, ScJob* j) {
     R.V_GS = j->V_GS;
     R.V_DS = j->V_DS;
     R.charge = j->d_charge;
-    R.U = j->dev->d_U;
+    R.U = j->d_Uptr;
     R.n_ref = j->d_nref;
     double* st = j->d_state;
     R.rho_in = st;
@@ -186,35 +225,126 @@ negf_status setup(negf_server* S, ScJob* j) {
     return NEGF_OK;
 }
 
-negf_job job_of(ScJob* j) {
-    negf_job q{};
-    q.dev = j->dev;
-    q.bias = j->bias;
-    q.n_c = (int)j->z_c.size();
-    q.z_c = j->d_zc;
-    q.w_c = j->d_wc;
-    q.n_r = (int)j->E_r.size();
-    q.E_r = j->d_Er;
-    q.w_r = j->d_wr;
-    q.charge = j->d_charge;
-    q.T = q.n_r ? j->d_T : nullptr;
-    q.current = j->d_cur;
-    q.sigma_cache = j->d_sigma;
-    q.sigma_mode = j->sigma_ready ? 2 : 1;
-    return q;
+negf_device* job_dev(ScJob* j, int k) { return j->modes ? j->modes->devs[k] : j->dev; }
+
+// the NEGF jobs of one request: one real-space job, or one scalar chain per mode
+void jobs_of(ScJob* j, std::vector<negf_job>& out) {
+    const int nj = j->n_jobs();
+    const size_t sig = j->ne_cap() * 2 * (j->modes ? 1 : (size_t)j->b * j->b);
+    for (int k = 0; k < nj; ++k) {
+        negf_job q{};
+        q.dev = job_dev(j, k);
+        q.bias = j->bias;
+        q.n_c = (int)j->z_c.size();
+        q.z_c = j->d_zc;
+        q.w_c = j->d_wc;
+        q.n_r = j->n_r;
+        q.E_r = j->d_Er;
+        q.w_r = j->d_wr;
+        q.charge = j->d_charge + (size_t)k * j->N * j->ring_width();
+        q.T = nullptr;
+        q.current = j->d_cur + k;
+        q.sigma_cache = j->d_sigma + (size_t)k * sig;
+        q.sigma_mode = j->sigma_ready ? 2 : 1;
+        out.push_back(q);
+    }
+}
+
+// Semi-adaptive grid (Section 3.3) at the request's current potential: the
+// integrand f_L A_L + f_R A_R of ring N/2 (atoms, or modes, summed) on the grid
+// of the guessed limits, then the refined grid written into the request's arrays.
+negf_status refresh_grid(negf_server* S, ScJob* j) {
+    double E_min, E_max, kT;
+    grid_window(j->bias, &E_min, &E_max, &kT);
+    const double l1 = clip(j->g_l1, E_min, E_max), l2 = clip(j->g_l2, E_min, E_max);
+    std::vector<double> Ep, Wp;
+    grid_parts(E_min, E_max, l1, l2, j->density, kT, Ep, Wp);
+    const int np = (int)Ep.size(), nj = j->n_jobs(), w = j->ring_width(), N = j->N;
+    const size_t Nbj = (size_t)N * w;
+    TRY(grow(S->ws, S->probe, ((size_t)2 * np + (size_t)nj * Nbj + nj) * 8));
+    double* pE = static_cast<double*>(S->probe.p);
+    double* pW = pE + np;
+    double* pq = pW + np;
+    HIPCHK(hipMemcpy(pE, Ep.data(), (size_t)np * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pW, Wp.data(), (size_t)np * 8, hipMemcpyHostToDevice));
+    std::vector<negf_job> jobs(nj);
+    for (int k = 0; k < nj; ++k) {
+        negf_job& q = jobs[k];
+        q = negf_job{};
+        q.dev = job_dev(j, k);
+        q.bias = j->bias;
+        q.n_r = np;
+        q.E_r = pE;
+        q.w_r = pW;
+        q.charge = pq + (size_t)k * Nbj;
+        q.current = pq + (size_t)nj * Nbj + k;
+    }
+    TRY(enqueue(S->ws, nj, jobs.data(), S->stream));
+    TRY(finish(S->ws, nullptr));
+    // A_L, A_R of ring N/2: job k's diagonals are [np][2][Nbj] at k np 2 Nbj
+    const int jc = N / 2;
+    std::vector<double> ad((size_t)nj * np * 2 * w);
+    const char* base = static_cast<const char*>(S->ws->ad.p);
+    for (int k = 0; k < nj; ++k)
+        HIPCHK(hipMemcpy2D(ad.data() + (size_t)k * np * 2 * w, (size_t)w * 8,
+                           base + ((size_t)k * np * 2 * Nbj + (size_t)jc * w) * 8, Nbj * 8, (size_t)w * 8,
+                           (size_t)2 * np, hipMemcpyDeviceToHost));
+    std::vector<double> g(np);
+    for (int e = 0; e < np; ++e) {
+        const double fl = host_fermi(Ep[e], j->bias.mu_L, j->bias.kT_L);
+        const double fr = host_fermi(Ep[e], j->bias.mu_R, j->bias.kT_R);
+        double acc = 0.0;
+        for (int k = 0; k < nj; ++k)
+            for (int i = 0; i < w; ++i) {
+                const double* row = ad.data() + ((size_t)k * np + e) * 2 * w;
+                acc += fl * row[i] + fr * row[w + i];
+            }
+        g[e] = acc;
+    }
+    double n1, n2, Es;
+    grid_refine(j->bias, Ep, g, l1, j->g_a, j->g_b, &n1, &n2, &Es);
+    std::vector<double> Ef, Wf;
+    grid_parts(E_min, E_max, n1, n2, j->density, kT, Ef, Wf);
+    if ((int)Ef.size() > j->n_r_cap)
+        return fail(NEGF_EINVAL, "refined grid of %d nodes exceeds its capacity %d", (int)Ef.size(), j->n_r_cap);
+    HIPCHK(hipMemcpy(j->d_Er, Ef.data(), Ef.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(j->d_wr, Wf.data(), Wf.size() * 8, hipMemcpyHostToDevice));
+    j->n_r = (int)Ef.size();
+    j->sigma_ready = false;      // the real-axis nodes moved: decimate again
+    return NEGF_OK;
 }
 
 void finish_job(negf_server* S, ScJob* j, int status) {
     j->status = status;
     j->t_done = now_ms();
-    const size_t Nb = (size_t)j->N * j->b;
-    if (j->dev && j->mem) {
+    const int N = j->N, b = j->b, nj = j->n_jobs();
+    const size_t Nb = (size_t)N * b;
+    if (j->mem && (j->dev || j->modes)) {
         j->charge_out.resize(Nb);
         j->U_out.resize(Nb);
-        if (hipMemcpy(j->charge_out.data(), j->d_charge, Nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(j->U_out.data(), j->dev->d_U, Nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(&j->current, j->d_cur, 8, hipMemcpyDeviceToHost) != hipSuccess)
+        std::vector<double> q(Nb), u(j->modes ? (size_t)N : Nb), cur(nj);
+        if (hipMemcpy(q.data(), j->d_charge, Nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(u.data(), job_dev(j, 0)->d_U, u.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(cur.data(), j->d_cur, (size_t)nj * 8, hipMemcpyDeviceToHost) != hipSuccess) {
             j->status = NEGF_EHIP;
+        } else if (j->modes) {
+            // per-atom charge: the ring's mode charges shared equally by its b atoms
+            for (int r = 0; r < N; ++r) {
+                double acc = 0.0;
+                for (int k = 0; k < nj; ++k) acc += q[(size_t)k * N + r];
+                for (int i = 0; i < b; ++i) {
+                    j->charge_out[(size_t)r * b + i] = acc / b;
+                    j->U_out[(size_t)r * b + i] = u[r];
+                }
+            }
+            double I = 0.0;
+            for (int k = 0; k < nj; ++k) I += cur[k];
+            j->current = I;
+        } else {
+            j->charge_out = q;
+            j->U_out = u;
+            j->current = cur[0];
+        }
     }
     release(j);
     std::lock_guard<std::mutex> lk(S->mu);
@@ -252,9 +382,31 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
     }
     if (S->running.empty()) return NEGF_OK;
 
+    // semi-adaptive grids due at this pass (before NEGF pass 1, 1 + refresh, ...)
+    {
+        std::vector<ScJob*> keep;
+        for (ScJob* j : S->running) {
+            if (j->adaptive && j->passes % j->refresh == 0) {
+                const negf_status st = refresh_grid(S, j);
+                if (st != NEGF_OK) {
+                    finish_job(S, j, st);
+                    continue;
+                }
+            }
+            keep.push_back(j);
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->running.swap(keep);
+    }
+    if (S->running.empty()) return NEGF_OK;
+
     // NEGF step of every running request, one batched solve
     std::vector<negf_job> jobs;
-    for (ScJob* j : S->running) jobs.push_back(job_of(j));
+    std::vector<int> first;
+    for (ScJob* j : S->running) {
+        first.push_back((int)jobs.size());
+        jobs_of(j, jobs);
+    }
     TRY(enqueue(S->ws, (int)jobs.size(), jobs.data(), S->stream));
     // self-consistency pass, one workgroup per request
     std::vector<negf::ScReq> rq;
@@ -275,10 +427,11 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
     }
     // per-request NEGF flags (ST_NOCONV: decimation; ST_BAD / ST_NOROOM: bad result)
     std::vector<ScJob*> keep;
-    for (size_t k = 0; k < S->running.size(); ++k) {
-        ScJob* j = S->running[k];
+    for (size_t r = 0; r < S->running.size(); ++r) {
+        ScJob* j = S->running[r];
         j->sigma_ready = true;
-        const int fl = S->ws->h_flags[kFlagInts * k];
+        int fl = 0;
+        for (int k = 0; k < j->n_jobs(); ++k) fl |= S->ws->h_flags[kFlagInts * (first[r] + k)];
         const int* st = S->h_stat + 4 * j->slot;
         j->passes = st[1];
         j->eps_max = S->h_diag[2 * j->slot];
@@ -392,8 +545,19 @@ negf_status negf_server_submit(negf_server* S, const negf_sc_request* r, long lo
     if (r->b < 1 || r->b > NEGF_MAX_RING) return fail(NEGF_EINVAL, "ring size %d", r->b);
     if (!r->h_diag || !r->h_up || !r->left || !r->right || !r->n_ref)
         return fail(NEGF_EINVAL, "request has a NULL array");
-    if (r->n_c < 0 || r->n_r < 0 || r->n_c + r->n_r < 1) return fail(NEGF_EINVAL, "no energy nodes");
-    if ((r->n_c && (!r->z_c || !r->w_c)) || (r->n_r && (!r->E_r || !r->w_r)))
+    if (r->basis < 0 || r->basis > 1) return fail(NEGF_EINVAL, "basis %d not 0 or 1", r->basis);
+    if (r->norm < 0 || r->norm > 1) return fail(NEGF_EINVAL, "norm %d not 0 or 1", r->norm);
+    const bool adaptive = r->grid_density[0] != 0 || r->grid_density[1] != 0 || r->grid_density[2] != 0;
+    if (adaptive) {
+        for (int p = 0; p < 3; ++p)
+            if (!(r->grid_density[p] > 0) || r->grid_density[p] > 1e6)
+                return fail(NEGF_EINVAL, "grid_density[%d] out of range", p);
+        if (!std::isfinite(r->grid_l1) || !std::isfinite(r->grid_l2) || !std::isfinite(r->grid_a) ||
+            !std::isfinite(r->grid_b) || r->grid_refresh < 0)
+            return fail(NEGF_EINVAL, "grid limits not finite or refresh interval negative");
+    }
+    if (r->n_c < 0 || r->n_r < 0 || (!adaptive && r->n_c + r->n_r < 1)) return fail(NEGF_EINVAL, "no energy nodes");
+    if ((r->n_c && (!r->z_c || !r->w_c)) || (!adaptive && r->n_r && (!r->E_r || !r->w_r)))
         return fail(NEGF_EINVAL, "grid arrays are NULL");
     if (!(r->dz > 0) || !(r->eps_1d > 0) || !(r->c_gate > 0)) return fail(NEGF_EINVAL, "electrostatics must be > 0");
     if (!(r->zeta > 0) || !(r->tol > 0) || r->max_iter < 1 || r->history < 0 ||
@@ -426,8 +590,45 @@ negf_status negf_server_submit(negf_server* S, const negf_sc_request* r, long lo
     j->bias = negf_bias{r->mu_S, r->mu_S - r->V_DS, r->kT, r->kT};
     j->z_c.assign(r->z_c, r->z_c + r->n_c);
     j->w_c.assign(r->w_c, r->w_c + r->n_c);
-    j->E_r.assign(r->E_r, r->E_r + r->n_r);
-    j->w_r.assign(r->w_r, r->w_r + r->n_r);
+    if (adaptive) {
+        j->adaptive = true;
+        double E_min, E_max, kT;
+        grid_window(j->bias, &E_min, &E_max, &kT);
+        double dmax = 0.0;
+        for (int p = 0; p < 3; ++p) {
+            j->density[p] = r->grid_density[p];
+            dmax = std::max(dmax, r->grid_density[p]);
+        }
+        // each part holds at most density x width / kT + 1 nodes
+        const double cap = std::floor(dmax * (E_max - E_min) / kT) + 4.0;
+        if (!(cap <= (double)(1 << 22))) {
+            delete j;
+            return fail(NEGF_EINVAL, "semi-adaptive grid of up to %.0f nodes", cap);
+        }
+        j->n_r_cap = (int)cap;
+        j->g_l1 = r->grid_l1;
+        j->g_l2 = r->grid_l2;
+        j->g_a = r->grid_a;
+        j->g_b = r->grid_b;
+        j->refresh = r->grid_refresh ? r->grid_refresh : 50;
+    } else {
+        j->E_r.assign(r->E_r, r->E_r + r->n_r);
+        j->w_r.assign(r->w_r, r->w_r + r->n_r);
+        j->n_r = j->n_r_cap = r->n_r;
+    }
+    j->norm = r->norm;
+    if (r->basis == 0) {   // mode space when every block is ring-circulant (the potential always is ring-uniform)
+        bool circ = true;
+        for (int k = 0; k < N && circ; ++k) circ = ring_circulant(r->h_diag + (size_t)k * b2, b);
+        for (int k = 0; k + 1 < N && circ; ++k) circ = ring_circulant(r->h_up + (size_t)k * b2, b);
+        for (int l = 0; l < 2 && circ; ++l) {
+            for (int q = 0; q < j->lead_period[l]; ++q)
+                circ = circ && ring_circulant(j->lead_hd[l].data() + q * b2, b) &&
+                       ring_circulant(j->lead_hu[l].data() + q * b2, b);
+            circ = circ && ring_circulant(j->lead_tau[l].data(), b);
+        }
+        j->want_modes = circ;
+    }
     j->n_ref.assign(r->n_ref, r->n_ref + N);
     const double e = 1.602176634e-19;
     j->a = r->eps_1d / (r->c_gate * r->dz * r->dz);
@@ -474,6 +675,8 @@ negf_status negf_server_poll(negf_server* S, long long id, int wait, negf_sc_res
         res->t_queue_ms = j->t_admit > 0 ? j->t_admit - j->t_submit : 0.0;
         res->t_run_ms = j->t_admit > 0 ? j->t_done - j->t_admit : 0.0;
         res->t_total_ms = j->t_done - j->t_submit;
+        res->n_r = j->n_r;
+        res->mode_space = j->want_modes ? 1 : 0;
     }
     if (charge && !j->charge_out.empty()) memcpy(charge, j->charge_out.data(), j->charge_out.size() * 8);
     if (U && !j->U_out.empty()) memcpy(U, j->U_out.data(), j->U_out.size() * 8);
@@ -512,6 +715,7 @@ void negf_server_destroy(negf_server* S) {
     if (S->d_stat) (void)hipFree(S->d_stat);
     if (S->d_diag) (void)hipFree(S->d_diag);
     if (S->d_reqs) (void)hipFree(S->d_reqs);
+    if (S->probe.p) (void)hipFree(S->probe.p);
     if (S->h_stat) (void)hipHostFree(S->h_stat);
     if (S->h_diag) (void)hipHostFree(S->h_diag);
     if (S->stream) (void)hipStreamDestroy(S->stream);

@@ -87,12 +87,15 @@ class negf_sc_request(C.Structure):
                 ("z_c", C.c_void_p), ("w_c", C.c_void_p), ("n_r", C.c_int), ("E_r", C.c_void_p),
                 ("w_r", C.c_void_p), ("dz", C.c_double), ("eps_1d", C.c_double), ("c_gate", C.c_double),
                 ("n_ref", C.c_void_p), ("zeta", C.c_double), ("tol", C.c_double), ("history", C.c_int),
-                ("max_iter", C.c_int)]
+                ("max_iter", C.c_int), ("basis", C.c_int), ("norm", C.c_int), ("grid_density", C.c_double * 3),
+                ("grid_l1", C.c_double), ("grid_l2", C.c_double), ("grid_a", C.c_double), ("grid_b", C.c_double),
+                ("grid_refresh", C.c_int)]
 
 
 class negf_sc_result(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("eps_max", C.c_double), ("current", C.c_double),
-                ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double), ("t_total_ms", C.c_double)]
+                ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("n_r", C.c_int), ("mode_space", C.c_int)]
 
 
 class negf_server_info(C.Structure):
@@ -581,7 +584,8 @@ class Server:
         self._sizes = {}
 
     def submit(self, req, precision: int = FP64) -> int:
-        """req: workload.ScRequest.  Returns the request id."""
+        """req: workload.ScRequest (its basis, norm and semi-adaptive grid settings
+        included).  Returns the request id."""
         dev, g, e = req.device, req.grid, req.elec
         keep = []
 
@@ -603,7 +607,13 @@ class Server:
                             req.bias.mu_L, req.bias.kT_L, e.V_DS, e.V_GS, g.n_c, arr(g.z_c, np.complex128),
                             arr(g.w_c, np.complex128), g.n_r, arr(g.E_r, np.float64), arr(g.w_r, np.float64),
                             e.dz, e.eps_1d, e.c_gate, arr(e.n_ref, np.float64), req.zeta, req.tol, req.history,
-                            req.max_iter)
+                            req.max_iter, req.basis, req.norm)
+        if req.grid_density is not None:
+            for p in range(3):
+                r.grid_density[p] = float(req.grid_density[p])
+            r.grid_l1, r.grid_l2 = (float(v) for v in req.grid_limits)
+            r.grid_a, r.grid_b = float(req.grid_a), float(req.grid_b)
+            r.grid_refresh = int(req.grid_refresh)
         rid = C.c_longlong()
         _check(load().negf_server_submit(self.h, C.byref(r), C.byref(rid)))
         self._sizes[rid.value] = (dev.n_rings * dev.b, req.max_iter)
@@ -623,7 +633,7 @@ class Server:
         self._sizes.pop(rid, None)
         return dict(status=res.status, iterations=res.iterations, eps_max=res.eps_max, current=res.current,
                     t_queue_ms=res.t_queue_ms, t_run_ms=res.t_run_ms, t_total_ms=res.t_total_ms, charge=charge,
-                    U=U, trace=tr[:res.iterations].copy())
+                    U=U, trace=tr[:res.iterations].copy(), n_r=res.n_r, mode_space=bool(res.mode_space))
 
     def stats(self) -> dict:
         info = negf_server_info()

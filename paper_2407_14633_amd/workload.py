@@ -380,6 +380,13 @@ class ScRequest:
     tol: float = 1e-5         # stop when max_j |f_j / (rho_in_j + rho_out_j)| < tol
     history: int = 8
     max_iter: int = 100
+    basis: int = 0            # 0: mode space when every block is ring-circulant; 1: real space
+    norm: int = 0             # 0: relative charge change (Algorithm 3); 1: potential residual (eV)
+    grid_density: Optional[tuple] = None   # (d1, d2, d3) nodes per kT: semi-adaptive real-axis grid
+    grid_limits: tuple = (0.0, 0.0)        # guessed E_l1, E_l2 of every rebuild (eV)
+    grid_a: float = 3.0
+    grid_b: float = 1.0
+    grid_refresh: int = 50    # NEGF passes between rebuilds (the first before pass 1)
     meta: dict = field(default_factory=dict)
 
     @property

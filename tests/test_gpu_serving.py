@@ -8,6 +8,7 @@
   request larger than the budget is refused at submission.
 """
 import sys
+from dataclasses import replace
 import time
 
 import numpy as np
@@ -46,8 +47,56 @@ def test_server_matches_oracle(gpu_lib, case):
     dU = np.max(np.abs(got["U"] - ref["U"]))
     dq = np.max(np.abs(got["charge"] - ref["charge"])) / np.max(np.abs(ref["charge"]))
     dI = abs(got["current"] - ref["current"]) / max(abs(ref["current"]), 1e-30)
-    say("dU", dU, "dq", dq, "dI", dI)
+    say("dU", dU, "dq", dq, "dI", dI, "mode space", got["mode_space"])
+    assert got["mode_space"]          # zigzag tubes are ring-circulant: the exact mode-space route
     assert dU < 1e-9 and dq < 1e-10 and dI < 1e-6
+
+
+def test_server_mode_space_equals_real_space(gpu_lib):
+    negf = gpu_lib
+    req = small_request(13, 28, 0.35, 0.2)
+    rs = replace(req, basis=1)
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        m = srv.poll(srv.submit(req))
+        r = srv.poll(srv.submit(rs))
+    dU = np.max(np.abs(m["U"] - r["U"]))
+    dq = np.max(np.abs(m["charge"] - r["charge"])) / np.max(np.abs(r["charge"]))
+    dI = abs(m["current"] - r["current"]) / abs(r["current"])
+    say("modes/real passes", m["iterations"], r["iterations"], "dU", dU, "dq", dq, "dI", dI)
+    assert m["mode_space"] and not r["mode_space"]
+    assert m["status"] == r["status"] == negf.NEGF_OK
+    assert m["iterations"] == r["iterations"]
+    assert dU < 1e-10 and dq < 1e-10 and dI < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_server_potential_stop_and_grid_refresh_match_oracle(gpu_lib, precision):
+    # eta = 1e-6, the 1e-6 eV potential-residual stop and a semi-adaptive grid
+    # rebuilt before passes 1, 3, 5, ... (every 2 passes, so that several rebuilds
+    # run inside the few passes of a small request)
+    negf = gpu_lib
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    req = small_request(10, 30, 0.4, -0.3, n_r=0, eta=1e-6, norm=1, tol=tol, grid_density=(2.0, 12.0, 4.0),
+                        grid_limits=(-0.3, 0.1), grid_refresh=2)
+    say("sc request", req.name, "eta", req.eta, "norm", req.norm, precision)
+    ref = S.self_consistent(req)
+    prec = negf.FP64 if precision == "fp64" else negf.FP32_BULK
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        got = srv.poll(srv.submit(req, precision=prec))
+    dU = np.max(np.abs(got["U"] - ref["U"]))
+    dq = np.max(np.abs(got["charge"] - ref["charge"])) / np.max(np.abs(ref["charge"]))
+    dI = abs(got["current"] - ref["current"]) / max(abs(ref["current"]), 1e-30)
+    say("passes gpu/oracle", got["iterations"], ref["iterations"], "n_r", got["n_r"], ref["n_r"], "eps",
+        got["eps_max"], ref["eps_max"], "dU", dU, "dq", dq, "dI", dI)
+    assert got["status"] == negf.NEGF_OK and ref["converged"] and got["mode_space"]
+    assert got["n_r"] == ref["n_r"]
+    assert ref["eps_max"] < tol and got["eps_max"] < tol
+    if precision == "fp64":
+        assert got["iterations"] == ref["iterations"]
+        assert dU < 1e-9 and dq < 1e-10 and dI < 1e-6
+    else:
+        assert abs(got["iterations"] - ref["iterations"]) <= 2
+        assert dU < 1e-5 and dq < 1e-5 and dI < 1e-4
 
 
 def test_server_alone_and_in_mix_bitwise(gpu_lib):

@@ -111,3 +111,48 @@ def test_gate_dominated_loop_stops_after_one_secant_step():
     assert np.allclose(res["phi"], 0.2, atol=1e-9)
     ref = O.solve(S.negf_problem(req, np.full(6 * 8, -0.2)))
     assert np.max(np.abs(res["charge"] - ref["charge"])) < 1e-7
+
+
+def test_potential_residual_is_the_poisson_difference():
+    # phi(rho_out) - phi(rho_in) from two full solves (gate and drain terms included)
+    # equals the homogeneous solve on f = rho_in - rho_out
+    N = 41
+    e = _elec(N, 3.0, V_DS=0.4, V_GS=-0.2)
+    rng = np.random.default_rng(11)
+    rho_in = e.n_ref + rng.normal(0, 0.05, N)
+    rho_out = e.n_ref + rng.normal(0, 0.05, N)
+    ref = S.poisson_rings(rho_out, e) - S.poisson_rings(rho_in, e)
+    got = S.potential_residual(rho_in - rho_out, e)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_potential_residual_point_charge_closed_form():
+    # one electron fewer on ring j0 (f = e_j0): psi_j = C r^|j-j0| with
+    # C (2k(1-r) + c) = +e/dz, the potential rises where the electron left
+    N, j0 = 101, 50
+    e = _elec(N, 1.0)
+    f = np.zeros(N)
+    f[j0] = 1.0
+    got = S.potential_residual(f, e)
+    k, c = e.eps_1d / e.dz ** 2, e.c_gate
+    q = 2.0 + c / k
+    r = 0.5 * (q - np.sqrt(q * q - 4.0))
+    C = (S.E_CHARGE / e.dz) / (2.0 * k * (1.0 - r) + c)
+    ref = C * r ** np.abs(np.arange(N) - j0)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_grid_rebuild_happens_before_the_first_pass():
+    # a semi-adaptive request whose only rebuild is the first one equals the
+    # fixed-grid request on the grid built at the first potential by hand
+    from dataclasses import replace
+
+    from oracle import grid_oracle as G
+    req = W.sc_request(8, 12, 0.3, 0.2, n_c=8, n_r=0, tol=1e-7, max_iter=4, grid_density=(1.0, 4.0, 2.0),
+                       grid_limits=(-0.25, 0.05), grid_refresh=1000)
+    U0 = S.ring_potential(S.poisson_rings(req.elec.n_ref, req.elec), req.device.b)
+    E_r, w_r, _ = G.semi_adaptive_grid(S.negf_problem(req, U0), -0.25, 0.05, 3.0, 1.0, (1.0, 4.0, 2.0))
+    fixed = replace(req, grid=W.EnergyGrid(req.grid.z_c, req.grid.w_c, E_r, w_r), grid_density=None)
+    a, b = S.self_consistent(req), S.self_consistent(fixed)
+    assert a["n_r"] == len(E_r) and a["iterations"] == b["iterations"]
+    assert np.array_equal(a["U"], b["U"]) and a["trace"] == b["trace"]
