@@ -690,12 +690,20 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     ev_begin(w, s, &ev);
     hipLaunchKernelGGL(negf::k_coef, dim3((max_ne + 255) / 256, n_jobs), dim3(256), 0, s, d_red);
     if (!decimation_only) {
-        for (int i = 0; i < n_jobs; ++i) {
-            const dim3 rgrid((unsigned)((plan[i].d->N * plan[i].d->b + 255) / 256), negf::RED_SEGS, 1);
-            if (plan[i].d->opt.precision == NEGF_FP32_BULK)
+        // one launch per run of consecutive jobs in the same precision (blockIdx.z: job in the run)
+        for (int i = 0; i < n_jobs;) {
+            const bool f32 = plan[i].d->opt.precision == NEGF_FP32_BULK;
+            int k = i, bx = 1;
+            while (k < n_jobs && k - i < 65535 && (plan[k].d->opt.precision == NEGF_FP32_BULK) == f32) {
+                bx = std::max(bx, (plan[k].d->N * plan[k].d->b + 255) / 256);
+                ++k;
+            }
+            const dim3 rgrid((unsigned)bx, negf::RED_SEGS, (unsigned)(k - i));
+            if (f32)
                 hipLaunchKernelGGL((negf::k_reduce_part<float, double>), rgrid, dim3(256), 0, s, d_red + i);
             else
                 hipLaunchKernelGGL((negf::k_reduce_part<double, double>), rgrid, dim3(256), 0, s, d_red + i);
+            i = k;
         }
         hipLaunchKernelGGL(negf::k_reduce_final, dim3((max_nb + 255) / 256, n_jobs), dim3(256), 0, s, d_red);
         hipLaunchKernelGGL(negf::k_current, dim3(n_jobs), dim3(64), 0, s, d_red);
@@ -931,8 +939,11 @@ void negf_default_options(negf_options* opt) {
 
 const char* negf_last_error(void) { return g_err.c_str(); }
 
-negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf_c64* h_diag, const negf_c64* h_up,
-                               const negf_lead* left, const negf_lead* right, const negf_options* opt) {
+}  // extern "C"
+
+negf_status negf_host::create_device(negf_device** out, int n_rings, int b, const negf_c64* h_diag,
+                                     const negf_c64* h_up, const negf_lead* left, const negf_lead* right,
+                                     const negf_options* opt, bool own_ws) {
     if (!out) return fail(NEGF_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_rings < 1) return fail(NEGF_EINVAL, "n_rings = %d < 1", n_rings);
@@ -1006,7 +1017,7 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
     };
     if (hipGetDevice(&d->dev_id) != hipSuccess) return bail(fail(NEGF_EHIP, "no HIP device"));
     negf_status s;
-    if ((s = ws_create(&d->ws, o.workspace_bytes ? o.workspace_bytes / 2 : 0)) != NEGF_OK) return bail(s);
+    if (own_ws && (s = ws_create(&d->ws, o.workspace_bytes ? o.workspace_bytes / 2 : 0)) != NEGF_OK) return bail(s);
 
     // max row sum of |H| over the device rows (on-site block, coupling to the next
     // ring and from the previous one): the scale of M in the FP32-bulk checks
@@ -1109,6 +1120,13 @@ negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf
     }
     *out = d;
     return NEGF_OK;
+}
+
+extern "C" {
+
+negf_status negf_create_device(negf_device** out, int n_rings, int b, const negf_c64* h_diag, const negf_c64* h_up,
+                               const negf_lead* left, const negf_lead* right, const negf_options* opt) {
+    return create_device(out, n_rings, b, h_diag, h_up, left, right, opt, true);
 }
 
 negf_status negf_set_potential(negf_device* d, const double* U, double U_left, double U_right) {

@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "negf_internal.hpp"
@@ -17,43 +19,88 @@ using namespace negf_host;
 
 namespace {
 
-// Gauss-Legendre nodes (ascending) and weights on [-1, 1] by Newton's method on P_n
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1] by Newton's method on P_n,
+// all roots at once (the three-term recurrence runs over k outside and over the
+// roots inside, with its coefficients (2k-1)/k and (k-1)/k tabulated).  Newton
+// converges quadratically from the asymptotic first guess: once a root's step is
+// below 1e-10, one more step reaches rounding level and that root stops.
+void gauss_legendre_newton(int n, std::vector<double>& x, std::vector<double>& w) {
     x.assign(n, 0.0);
     w.assign(n, 0.0);
+    if (n < 1) return;
     const double pi = 3.14159265358979323846;
-    for (int i = 0; i < (n + 1) / 2; ++i) {
-        double z = std::cos(pi * (i + 0.75) / (n + 0.5));
-        double dp = 0.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = z;   // P_0, P_1
-            for (int k = 2; k <= n; ++k) {
-                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            const double pn = n == 0 ? 1.0 : (n == 1 ? z : p1);
-            const double pm = n == 1 ? 1.0 : p0;   // P_{n-1}
-            dp = n * (z * pn - pm) / (z * z - 1.0);
-            const double dz = pn / dp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-16) break;
+    const int m = (n + 1) / 2;
+    std::vector<double> z(m), p0(m), p1(m), ak(n + 1, 0.0), ck(n + 1, 0.0);
+    std::vector<char> live(m, 1), polish(m, 0);
+    for (int k = 2; k <= n; ++k) {
+        ak[k] = (2.0 * k - 1.0) / k;
+        ck[k] = (k - 1.0) / k;
+    }
+    for (int i = 0; i < m; ++i) z[i] = std::cos(pi * (i + 0.75) / (n + 0.5));
+    auto legendre = [&]() {   // p1 = P_n(z), p0 = P_{n-1}(z) at every root
+        for (int i = 0; i < m; ++i) {
+            p0[i] = 1.0;
+            p1[i] = z[i];
         }
-        // recompute the derivative at the converged root
-        double p0 = 1.0, p1 = z;
         for (int k = 2; k <= n; ++k) {
-            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-            p0 = p1;
-            p1 = p2;
+            const double a = ak[k], c = ck[k];
+            for (int i = 0; i < m; ++i) {
+                const double p2 = a * z[i] * p1[i] - c * p0[i];
+                p0[i] = p1[i];
+                p1[i] = p2;
+            }
         }
-        dp = n * (z * (n == 1 ? z : p1) - (n == 1 ? 1.0 : p0)) / (z * z - 1.0);
-        const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
-        x[i] = -z;
-        x[n - 1 - i] = z;
+    };
+    for (int it = 0; it < 100; ++it) {
+        legendre();
+        int n_live = 0;
+        for (int i = 0; i < m; ++i) {
+            if (!live[i]) continue;
+            const double dp = n * (z[i] * p1[i] - p0[i]) / (z[i] * z[i] - 1.0);
+            const double dz = p1[i] / dp;
+            z[i] -= dz;
+            if (std::fabs(dz) < 1e-16 || polish[i])
+                live[i] = 0;
+            else
+                polish[i] = std::fabs(dz) < 1e-10;
+            n_live += live[i];
+        }
+        if (!n_live) break;
+    }
+    legendre();   // the derivative at the converged roots
+    for (int i = 0; i < m; ++i) {
+        const double dp = n * (z[i] * p1[i] - p0[i]) / (z[i] * z[i] - 1.0);
+        const double wi = 2.0 / ((1.0 - z[i] * z[i]) * dp * dp);
+        x[i] = -z[i];
+        x[n - 1 - i] = z[i];
         w[i] = wi;
         w[n - 1 - i] = wi;
     }
     if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// Rules already built, by order (each costs O(n^2)); at most 64 MiB are kept.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    static std::mutex mu;
+    static std::map<int, std::pair<std::vector<double>, std::vector<double>>> cache;
+    static size_t cached = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(n);
+        if (it != cache.end()) {
+            x = it->second.first;
+            w = it->second.second;
+            return;
+        }
+    }
+    gauss_legendre_newton(n, x, w);
+    std::lock_guard<std::mutex> lk(mu);
+    if (cached + (size_t)n * 16 > ((size_t)64 << 20)) {
+        cache.clear();
+        cached = 0;
+    }
+    cache[n] = {x, w};
+    cached += (size_t)n * 16;
 }
 
 double clip(double v, double lo, double hi) { return std::min(std::max(v, lo), hi); }

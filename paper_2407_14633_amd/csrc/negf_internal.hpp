@@ -134,6 +134,12 @@ negf_status finish(negf_workspace* w, int* failed_job);
 negf_status ws_create(negf_workspace** out, size_t store_bytes);
 void ws_destroy(negf_workspace* w);
 
+// negf_create_device; own_ws = false leaves out the handle's private workspace
+// (stream, event, pinned flags), for devices that only ever run in batches on a
+// caller's workspace (the scalar chains of a mode-space tube).
+negf_status create_device(negf_device** out, int n_rings, int b, const negf_c64* h_diag, const negf_c64* h_up,
+                          const negf_lead* left, const negf_lead* right, const negf_options* opt, bool own_ws);
+
 // Ring-circulant test of a b x b block: M[i][j] == M[0][(j - i) mod b], exactly.
 bool ring_circulant(const negf_c64* M, int b);
 

@@ -105,8 +105,8 @@ negf_status negf_modes_create(negf_modes** out, int n_rings, int b, const negf_c
             sl[l] = negf_lead{L->period, lhd[l].data(), lhu[l].data(), lt[l].data()};
         }
         negf_device* d = nullptr;
-        const negf_status st = negf_create_device(&d, n_rings, 1, hd.data(), n_rings > 1 ? hu.data() : nullptr, &sl[0],
-                                                  &sl[1], opt);
+        const negf_status st =
+            create_device(&d, n_rings, 1, hd.data(), n_rings > 1 ? hu.data() : nullptr, &sl[0], &sl[1], opt, false);
         if (st != NEGF_OK) {
             const std::string msg = g_err;
             negf_modes_destroy(m);

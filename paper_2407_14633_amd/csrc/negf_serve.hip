@@ -225,6 +225,17 @@ negf_status setup(negf_server* S, ScJob* j) {
     return NEGF_OK;
 }
 
+// gathers the A_L, A_R diagonals of ring jc from the probe's per-job arrays
+// [n_jobs][np][2][N w] into out[n_jobs][np][2][w]
+__global__ void k_gather_ring(const double* ad, double* out, int n_jobs, int np, int Nw, int jc, int w) {
+    const long long n = (long long)n_jobs * np * 2 * w;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % w);
+        const long long row = q / w;   // (job, node, lead)
+        out[q] = ad[row * Nw + (long long)jc * w + i];
+    }
+}
+
 negf_device* job_dev(ScJob* j, int k) { return j->modes ? j->modes->devs[k] : j->dev; }
 
 // the NEGF jobs of one request: one real-space job, or one scalar chain per mode
@@ -261,10 +272,12 @@ negf_status refresh_grid(negf_server* S, ScJob* j) {
     grid_parts(E_min, E_max, l1, l2, j->density, kT, Ep, Wp);
     const int np = (int)Ep.size(), nj = j->n_jobs(), w = j->ring_width(), N = j->N;
     const size_t Nbj = (size_t)N * w;
-    TRY(grow(S->ws, S->probe, ((size_t)2 * np + (size_t)nj * Nbj + nj) * 8));
+    const size_t n_ring = (size_t)nj * np * 2 * w;   // gathered diagonals of ring N/2
+    TRY(grow(S->ws, S->probe, ((size_t)2 * np + (size_t)nj * Nbj + nj + n_ring) * 8));
     double* pE = static_cast<double*>(S->probe.p);
     double* pW = pE + np;
     double* pq = pW + np;
+    double* pg = pq + (size_t)nj * Nbj + nj;
     HIPCHK(hipMemcpy(pE, Ep.data(), (size_t)np * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(pW, Wp.data(), (size_t)np * 8, hipMemcpyHostToDevice));
     std::vector<negf_job> jobs(nj);
@@ -283,12 +296,12 @@ negf_status refresh_grid(negf_server* S, ScJob* j) {
     TRY(finish(S->ws, nullptr));
     // A_L, A_R of ring N/2: job k's diagonals are [np][2][Nbj] at k np 2 Nbj
     const int jc = N / 2;
-    std::vector<double> ad((size_t)nj * np * 2 * w);
-    const char* base = static_cast<const char*>(S->ws->ad.p);
-    for (int k = 0; k < nj; ++k)
-        HIPCHK(hipMemcpy2D(ad.data() + (size_t)k * np * 2 * w, (size_t)w * 8,
-                           base + ((size_t)k * np * 2 * Nbj + (size_t)jc * w) * 8, Nbj * 8, (size_t)w * 8,
-                           (size_t)2 * np, hipMemcpyDeviceToHost));
+    std::vector<double> ad(n_ring);
+    hipLaunchKernelGGL(k_gather_ring, dim3((unsigned)std::min<size_t>((n_ring + 255) / 256, 4096)), dim3(256), 0,
+                       S->stream, static_cast<const double*>(S->ws->ad.p), pg, nj, np, (int)Nbj, jc, w);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ad.data(), pg, n_ring * 8, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
     std::vector<double> g(np);
     for (int e = 0; e < np; ++e) {
         const double fl = host_fermi(Ep[e], j->bias.mu_L, j->bias.kT_L);

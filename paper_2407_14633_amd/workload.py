@@ -423,13 +423,17 @@ def sc_request(n: int, N: int, V_DS: float, V_GS: float, n_c: int, n_r: int, mu_
 
 
 def serving_requests(n_req: int, seed: int = 5555, chiralities=(10, 13, 17, 20, 23), N_range=(200, 2000),
-                     ne_range=(512, 4096), contour_frac: float = 0.25, eta: float = 1e-3, **kw) -> list:
+                     ne_range=(512, 4096), contour_frac: float = 0.25, eta: float = 1e-6, adaptive: bool = True,
+                     norm: int = 1, tol: float = 1e-6, grid_refresh: int = 50, **kw) -> list:
     """Requests drawn like the batching workload, with V_DS ~ U[0, 0.6] and V_GS ~ U[-0.5, 0.5].
 
-    eta = 1e-3 eV: with a few thousand fixed real-axis nodes, resonances of
-    linewidth 1e-6 eV in long channels are not resolved, the computed charge then
-    jumps as the potential moves them across nodes, and the mixing stalls near
-    1e-4; a 1e-3 eV broadening makes the charge a smooth function of U."""
+    The drawn energy count ne sets the contour part (contour_frac of it) and the
+    real-axis budget n_r = ne - n_c.  adaptive: the real axis is the semi-adaptive
+    grid (Section 3.3) with densities (0.5, 2, 0.5) x n_r kT / (E_max - E_min) nodes
+    per kT in its three parts, guessed limits (mu_R, mu_L), rebuilt before the
+    first pass and every grid_refresh passes; otherwise n_r fixed Gauss-Legendre
+    nodes.  norm = 1, tol = 1e-6: stop when the output charge would move the
+    potential by less than 1e-6 eV."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n_req):
@@ -439,7 +443,18 @@ def serving_requests(n_req: int, seed: int = 5555, chiralities=(10, 13, 17, 20, 
         n_c = int(round(contour_frac * ne))
         V_DS = float(rng.uniform(0.0, 0.6))
         V_GS = float(rng.uniform(-0.5, 0.5))
-        out.append(sc_request(n, N, V_DS, V_GS, n_c, ne - n_c, eta=eta, **kw))
+        n_r = ne - n_c
+        if adaptive:
+            r = sc_request(n, N, V_DS, V_GS, n_c, 0, eta=eta, norm=norm, tol=tol, **kw)
+            E_min, E_max = window(r.bias)
+            kT = min(r.bias.kT_L, r.bias.kT_R)
+            rho = n_r * kT / (E_max - E_min)
+            r.grid_density = (0.5 * rho, 2.0 * rho, 0.5 * rho)
+            r.grid_limits = (min(r.bias.mu_L, r.bias.mu_R), max(r.bias.mu_L, r.bias.mu_R))
+            r.grid_refresh = grid_refresh
+        else:
+            r = sc_request(n, N, V_DS, V_GS, n_c, n_r, eta=eta, norm=norm, tol=tol, **kw)
+        out.append(r)
     return out
 
 
