@@ -311,13 +311,13 @@ def bench_batch(a):
 
 
 def run_serving(n_req: int, rate: float, seed: int = 5555, precision=None, max_inflight: int = 64,
-                adaptive: bool = True) -> dict:
+                adaptive: bool = True, eta: float = 1e-6) -> dict:
     """Poisson arrivals of self-consistent bias-point requests (devices drawn like the batch
     workload, V_DS ~ U[0,0.6], V_GS ~ U[-0.5,0.5]; eta 1e-6, semi-adaptive real axis, stop at
     a 1e-6 eV potential residual) served with continuous batching."""
     from paper_2407_14633_amd import negf
     precision = negf.FP32_BULK if precision is None else precision
-    reqs = W.serving_requests(n_req, seed, adaptive=adaptive)
+    reqs = W.serving_requests(n_req, seed, adaptive=adaptive, eta=eta)
     arrivals = W.poisson_arrivals(n_req, rate, seed + 1)
     import torch
     free, total = torch.cuda.mem_get_info()
@@ -357,18 +357,30 @@ def run_serving(n_req: int, rate: float, seed: int = 5555, precision=None, max_i
             "workload": f"{n_req} requests, Poisson arrivals at {rate} req/s (seed {seed})"}
 
 
-def serving_sweep(n_req: int, rates, precision=None) -> dict:
-    """run_serving at each offered rate; the knee is the throughput the server sustains at
-    the highest rate when it falls short of that rate (else: above the highest rate)."""
-    runs = [run_serving(n_req, r, precision=precision) for r in rates]
-    for r in runs:
-        log("serving", r)
+def _knee(runs) -> dict:
     top = runs[-1]
     sat = top["throughput_req_per_s"] < 0.9 * top["rate_req_per_s"]
-    return {"runs": runs, "knee_req_per_s": top["throughput_req_per_s"] if sat else None,
+    return {"knee_req_per_s": top["throughput_req_per_s"] if sat else None,
             "knee": (f"saturates near {top['throughput_req_per_s']:.1f} req/s (offered {top['rate_req_per_s']})"
-                     if sat else f"not reached: keeps up with {top['rate_req_per_s']} req/s"),
-            "precision": top["precision"], "requests_per_rate": n_req}
+                     if sat else f"not reached: keeps up with {top['rate_req_per_s']} req/s")}
+
+
+def serving_sweep(n_req: int, rates, precision=None, etas=(1e-6, 1e-3)) -> dict:
+    """run_serving at each offered rate, for each broadening; the knee is the throughput the
+    server sustains at the highest rate when it falls short of that rate."""
+    out = {"requests_per_rate": n_req}
+    for k, eta in enumerate(etas):
+        runs = []
+        for r in rates:
+            runs.append(run_serving(n_req, r, precision=precision, eta=eta))
+            log("serving", runs[-1])
+        entry = {"eta": eta, "runs": runs, **_knee(runs)}
+        if k == 0:
+            out.update(entry)
+            out["precision"] = runs[-1]["precision"]
+        else:
+            out[f"eta_{eta:g}"] = entry
+    return out
 
 
 def _current_diffs(c32, c64) -> dict:

@@ -583,6 +583,90 @@ __device__ __forceinline__ void add_a_row(const JobDesc& J, int e, int n, int r,
     }
 }
 
+// ======================================================= scalar (B = 1) paths ==
+// a_n - state for a ring of size 1, formed in FP64: z - H_nn - U_n - Sigma (boundary
+// rings) - state.
+__device__ __forceinline__ cx<double> scalar_a(const JobDesc& J, int e, int n, double u, cx<double> z) {
+    double re = z.re - u, im = z.im;
+    if (!J.hdiag_zero) {
+        const cx<double> h = gload(J.hdiag + n);
+        re -= h.re;
+        im -= h.im;
+    }
+    if (n == 0) {
+        const cx<double> sv = gload(J.sigma + (size_t)e * 2 + 0);
+        re -= sv.re;
+        im -= sv.im;
+    }
+    if (n == J.N - 1) {
+        const cx<double> sv = gload(J.sigma + (size_t)e * 2 + 1);
+        re -= sv.re;
+        im -= sv.im;
+    }
+    return cx<double>{re, im};
+}
+
+// One chain of k_recur for ring size 1 (the same quantities and store slots as
+// the block form): inv = (a_n - state)^{-1}; real nodes store t = inv p (the P
+// product, x~/y~), contour nodes the next state q t; the last ring stores
+// G_{N-1,N-1} (forward, slot 0) or G_00 (backward, slot N-1) for real nodes.
+// FP32-bulk: the two rings with a lead self-energy are inverted in FP64.
+template <typename T>
+__device__ __forceinline__ void recur_scalar(const JobDesc& J, int dir, int e, bool contour, cx<double> z,
+                                             cx<T>* store, const cx<T>* s_eval) {
+    constexpr bool kF32 = sizeof(T) == 4;
+    const int N = J.N, K = J.K;
+    T yr = T(0), yi = T(0);
+    double u_next = gload_s(J.U + (dir ? N - 1 : 0));
+    // coupling-table offset of the step's block, loaded a step ahead
+    int base_next = N > 1 ? gload_s(J.ell_map + (dir ? N - 2 : 0)) * K : 0;
+    for (int s = 0; s < N; ++s) {
+        const int n = dir ? N - 1 - s : s;
+        const bool last = (s == N - 1);
+        if (last && contour) break;
+        const double uu = u_next;
+        if (!last) u_next = gload_s(J.U + (dir ? N - 2 - s : s + 1));
+        const int base = base_next;
+        if (s + 2 < N) base_next = gload_s(J.ell_map + (dir ? N - 3 - s : s + 1)) * K;
+        T ir, ii;
+        if (!kF32 || s == 0 || last) {
+            const cx<double> a = scalar_a(J, e, n, uu, z);
+            const double mr = a.re - (double)yr, mi = a.im - (double)yi;
+            double qr, qi;
+            pivot_recip(mr, mi, qr, qi);
+            ir = T(qr);
+            ii = T(qi);
+        } else {
+            T mr = T(z.re - uu) - yr, mi = T(z.im) - yi;
+            if (!J.hdiag_zero) {
+                const cx<double> h = gload(J.hdiag + n);
+                mr -= T(h.re);
+                mi -= T(h.im);
+            }
+            pivot_recip(mr, mi, ir, ii);
+        }
+        if (last) {
+            gstore(store + (dir ? N - 1 : 0), cx<T>{ir, ii});
+            break;
+        }
+        const int slot = dir ? N - 2 - s : s + 1;
+        T hr = T(0), hi = T(0);
+        for (int t = 0; t < K; ++t) {
+            const cx<T> h = s_eval[base + t];
+            hr += h.re;
+            hi += h.im;
+        }
+        // P product: fwd p = -h, bwd p = -conj(h);  Q product: fwd q = -conj(h), bwd q = -h
+        const T pr = -hr, pi = dir ? hi : -hi;
+        const T tr = fma(ir, pr, -(ii * pi)), ti = fma(ir, pi, ii * pr);
+        if (!contour) gstore(store + slot, cx<T>{tr, ti});
+        const T qr = -hr, qi = dir ? -hi : hi;
+        yr = fma(qr, tr, -(qi * ti));
+        yi = fma(qr, ti, qi * tr);
+        if (contour) gstore(store + slot, cx<T>{yr, yi});
+    }
+}
+
 // ================================================================ k_recur ==
 // Chain = (node, direction).  Direction 0 (forward) runs the left-connected
 // recursion y_{n+1} = c_n (a_n - y_n)^{-1} b_n; direction 1 (backward) runs the
@@ -661,6 +745,13 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             }
         }
         const cx<double> z = gload(J.z + e);
+        if constexpr (B == 1) {
+            // scalar chains (ring size 1, e.g. one mode of a mode-space tube): one chain
+            // per lane, state in registers, no exchange between lanes
+            if (act) recur_scalar<T>(J, dir, e, contour, z, store, s_eval);
+            wave_sync();
+            continue;
+        }
         double u_next = act ? gload_s(J.U + (size_t)(dir ? N - 1 : 0) * B + r) : 0.0;
         // the recursion state (y_n or x_n) is kept in the group's stage between steps
         stage_row<T, B>(zero_row<T, B>(), zero_row<T, B>(), g.stage, r, act);
@@ -781,6 +872,33 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         const int e = u.e0 + el;                 // node inside the job
         const int n = item - el * N;
         const size_t o_row = u.off + ((size_t)el * N + n) * B * B + (size_t)r * B;
+        if constexpr (B == 1) {   // scalar chains: one item per lane, no exchange
+            if (live) {
+                const cx<T> zero{T(0), T(0)};
+                const cx<T> y = n > 0 ? gload(reinterpret_cast<const cx<T>*>(S.store_f) + o_row) : zero;
+                const cx<T> x = n < N - 1 ? gload(reinterpret_cast<const cx<T>*>(S.store_b) + o_row) : zero;
+                const double uu = gload_s(J.U + n);
+                const cx<double> z = gload(J.z + e);
+                cx<T>* out = reinterpret_cast<cx<T>*>(J.gr_diag) + (size_t)e * N + n;
+                if (!kF32 || n == 0 || n == N - 1) {
+                    const cx<double> a = scalar_a(J, e, n, uu, z);
+                    double qr, qi;
+                    pivot_recip(a.re - (double)y.re - (double)x.re, a.im - (double)y.im - (double)x.im, qr, qi);
+                    gstore(out, cx<T>{T(qr), T(qi)});
+                } else {
+                    T mr = T(z.re - uu) - y.re - x.re, mi = T(z.im) - y.im - x.im;
+                    if (!J.hdiag_zero) {
+                        const cx<double> h = gload(J.hdiag + n);
+                        mr -= T(h.re);
+                        mi -= T(h.im);
+                    }
+                    T qr, qi;
+                    pivot_recip(mr, mi, qr, qi);
+                    gstore(out, cx<T>{qr, qi});
+                }
+            }
+            continue;
+        }
         // FP32-bulk: the rings that carry a lead self-energy are inverted in FP64
         const bool bnd = kF32 && (n == 0 || n == N - 1);
         if constexpr (kF32) {
@@ -862,6 +980,56 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #ifndef NEGF_FP32_WMAX
 #define NEGF_FP32_WMAX 16.0
 #endif
+// One chain of k_column for ring size 1: W starts at G_{N-1,N-1} (right lead,
+// forward store slot 0) or G_00 (left lead, backward store slot N-1) and moves
+// by W <- -p_n W with p_n the stored x~/y~ of ring n; A_n = gamma |W_n|^2 with
+// gamma = i (Sigma - conj Sigma) = -2 Im Sigma of this lead, and at the far end
+// T = gamma_other gamma |W|^2.  The same output checks as the block form.
+template <typename TS>
+__device__ __forceinline__ void column_scalar(const JobDesc& J, const cx<TS>* store, int lead, int e, int ir) {
+    const int N = J.N;
+    const double gl = -2.0 * gload(J.sigma + (size_t)e * 2 + lead).im;
+    const double go = -2.0 * gload(J.sigma + (size_t)e * 2 + (1 - lead)).im;
+    const cx<TS> w0 = gload(store + (lead ? 0 : N - 1));
+    double wr = (double)w0.re, wi = (double)w0.im;
+    double* aout = reinterpret_cast<double*>(J.a_diag) + ((size_t)ir * 2 + lead) * N;
+    double wmax = 0.0, amn = 0.0, amx = 0.0;
+    // the propagators of the next four rings are in flight while a ring is processed
+    const cx<TS> z0{TS(0), TS(0)};
+    auto prop = [&](int s) { return s < N - 1 ? gload(store + (lead ? N - 1 - s : s)) : z0; };
+    cx<TS> p1 = prop(0), p2 = prop(1), p3 = prop(2), p4 = prop(3);
+    for (int s = 0; s < N; ++s) {
+        const int n = lead ? N - 1 - s : s;
+        const cx<TS> p = p1;
+        p1 = p2;
+        p2 = p3;
+        p3 = p4;
+        p4 = prop(s + 4);
+        const double acc = gl * fma(wr, wr, wi * wi);
+        gstore_s(aout + n, acc);
+        wmax = fmax(wmax, fabs(wr) + fabs(wi));
+        amn = s == 0 ? acc : fmin(amn, acc);
+        amx = s == 0 ? acc : fmax(amx, acc);
+        if (s == N - 1) break;
+        const double pr = -(double)p.re, pi = -(double)p.im;
+        const double nr = fma(pr, wr, -(pi * wi)), ni = fma(pr, wi, pi * wr);
+        wr = nr;
+        wi = ni;
+    }
+    const double tsum = go * gl * fma(wr, wr, wi * wi);
+    gstore_s((lead == 1 ? J.Tout : J.Trl) + ir, tsum);
+    gstore_s(J.amax + 2 * ir + lead, amx);
+    const bool bad_T = !(tsum >= -1e-6 && tsum <= 1.0 + 1e-6);
+    const bool bad_A = !(amn >= -1e-6 * fabs(amx)) || !(amx < 1e300);
+    if constexpr (sizeof(TS) == 4) {
+        const cx<double> z = gload(J.z + e);
+        const bool big_w = wmax * (fabs(z.re) + fabs(z.im) + J.hnorm) > NEGF_FP32_WMAX;
+        if (bad_T || bad_A || big_w) atomicOr(&J.status[e], (int)ST_FP64);
+    } else {
+        if (bad_T || bad_A) atomicOr(&J.status[e], (int)ST_BAD);
+    }
+}
+
 template <typename TS, int B>
 __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per_eu(NEGF_RGF_WAVES, NEGF_RGF_WAVES))) void k_column(Sched S) {
     using T = double;
@@ -887,6 +1055,13 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         const int N = J.N;
         const int e = u.e0 + (act ? gi : 0);     // node index within the job (>= n_c)
         const int ir = e - J.n_c;                 // real-axis index
+        if constexpr (B == 1) {   // scalar chains: one chain per lane
+            if (act)
+                column_scalar<TS>(J, reinterpret_cast<const cx<TS>*>(lead ? S.store_f : S.store_b) + u.off +
+                                         (size_t)(u.i0 + gi) * N,
+                                  lead, e, ir);
+            continue;
+        }
         wave_sync();
         if (act) {
             const cx<double>* s = J.sigma + ((size_t)e * 2 + lead) * B * B;
