@@ -63,6 +63,11 @@ enum { NEGF_MAX_RING = 24, NEGF_MAX_PERIOD = 2 };
  *   h_up  [period][b][b]  h_up[r] = H_{ring r, ring r+1}; h_up[period-1] couples to
  *                         ring 0 of the next cell
  *   tau   [b][b]          H_{device edge ring, lead ring 0}; Sigma = tau g_00 tau^H
+ * This is the paper's contact (Section 2.2.1: each contact continues the tube
+ * semi-infinitely): a principal layer of one or two rings of the device's ring
+ * size, coupled to the next layer only through its last ring.  A generic dense
+ * layer {m, h00, h01, tau} with couplings beyond adjacent rings, or more than two
+ * rings per layer, is not expressible: EINVAL for period outside [1, 2].
  */
 typedef struct {
     int period;

@@ -53,6 +53,8 @@ def _create(lib, N=4, b=3, period=2, h_diag="ok", h_up="ok", left="ok", right="o
         l = NG.negf_lead(ld.period, *(a.ctypes.data_as(C.c_void_p) for a in arrs))
         if mode == "badperiod":
             l.period = 3
+        if mode == "zeroperiod":
+            l.period = 0
         if mode == "nulltau":
             l.tau = None
         return C.byref(l)
@@ -75,7 +77,8 @@ def _create(lib, N=4, b=3, period=2, h_diag="ok", h_up="ok", left="ok", right="o
     (dict(h_diag=None), "h_diag"),
     (dict(h_up=None), "h_up"),
     (dict(left=None), "left lead"),
-    (dict(right="badperiod"), "period"),
+    (dict(right="badperiod"), "period"),      # a principal layer of more than two rings
+    (dict(left="zeroperiod"), "period"),
     (dict(left="nulltau"), "NULL block"),
     (dict(opt=dict(precision=7)), "precision"),
     (dict(opt=dict(decim_tol=0.0)), "decim_tol"),
