@@ -540,7 +540,9 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
             }
             store_need = std::max(store_need, used * cbs);
             TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, rec, 2, 0, gpw, false, dyn));
-            TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, gpw, true, 0));
+            // ring size 1: 16 items per lane and unit (one unit claim and span search per 1024 items)
+            TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0,
+                           B == 1 ? negf::CDIAG1_ITEMS : gpw, true, 0));
             TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, gpw, false,
                            0));
             if (g.f32) gcol[gi].insert(gcol[gi].end(), col.begin(), col.end());

@@ -471,6 +471,9 @@ struct JobDesc {
 // each unit once per side (direction or lead).  Units are numbered span by
 // span: first[s] = units before span s, so unit w belongs to the span with
 // first[s] <= w < first[s+1], and within it side = local % sides.
+// k_cdiag items per unit at ring size 1 (16 per lane)
+constexpr int CDIAG1_ITEMS = 1024;
+
 struct Span {
     int job, e0, cnt, pad;
     long long off;            // store element offset of node e0 (recursion stores)
@@ -872,23 +875,44 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         const int e = u.e0 + el;                 // node inside the job
         const int n = item - el * N;
         const size_t o_row = u.off + ((size_t)el * N + n) * B * B + (size_t)r * B;
-        if constexpr (B == 1) {   // scalar chains: one item per lane, no exchange
-            if (live) {
+        if constexpr (B == 1) {   // scalar chains: CDIAG1_ITEMS / 64 items per lane, no exchange
+            constexpr int M = CDIAG1_ITEMS / 64;
+            const int N1 = N - 1;
+            cx<T> ys[M], xs[M];
+            double us[M];
+            int es[M], ns[M];
+            bool ok[M];
+            // every item's operands first, so that their loads are in flight together
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int item = u.i0 + k * 64 + lane;
+                ok[k] = item < n_items && k * 64 < S.gpw;
+                const int el = ok[k] ? item / N : 0;
+                const int nn = ok[k] ? item - el * N : 0;
+                es[k] = u.e0 + el;
+                ns[k] = nn;
+                const size_t o = u.off + (size_t)el * N + nn;
                 const cx<T> zero{T(0), T(0)};
-                const cx<T> y = n > 0 ? gload(reinterpret_cast<const cx<T>*>(S.store_f) + o_row) : zero;
-                const cx<T> x = n < N - 1 ? gload(reinterpret_cast<const cx<T>*>(S.store_b) + o_row) : zero;
-                const double uu = gload_s(J.U + n);
+                ys[k] = ok[k] && nn > 0 ? gload(reinterpret_cast<const cx<T>*>(S.store_f) + o) : zero;
+                xs[k] = ok[k] && nn < N1 ? gload(reinterpret_cast<const cx<T>*>(S.store_b) + o) : zero;
+                us[k] = ok[k] ? gload_s(J.U + nn) : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                if (!ok[k]) continue;
+                const int e = es[k], nn = ns[k];
                 const cx<double> z = gload(J.z + e);
-                cx<T>* out = reinterpret_cast<cx<T>*>(J.gr_diag) + (size_t)e * N + n;
-                if (!kF32 || n == 0 || n == N - 1) {
-                    const cx<double> a = scalar_a(J, e, n, uu, z);
+                cx<T>* out = reinterpret_cast<cx<T>*>(J.gr_diag) + (size_t)e * N + nn;
+                if (!kF32 || nn == 0 || nn == N1) {
+                    const cx<double> a = scalar_a(J, e, nn, us[k], z);
                     double qr, qi;
-                    pivot_recip(a.re - (double)y.re - (double)x.re, a.im - (double)y.im - (double)x.im, qr, qi);
+                    pivot_recip(a.re - (double)ys[k].re - (double)xs[k].re, a.im - (double)ys[k].im - (double)xs[k].im,
+                                qr, qi);
                     gstore(out, cx<T>{T(qr), T(qi)});
                 } else {
-                    T mr = T(z.re - uu) - y.re - x.re, mi = T(z.im) - y.im - x.im;
+                    T mr = T(z.re - us[k]) - ys[k].re - xs[k].re, mi = T(z.im) - ys[k].im - xs[k].im;
                     if (!J.hdiag_zero) {
-                        const cx<double> h = gload(J.hdiag + n);
+                        const cx<double> h = gload(J.hdiag + nn);
                         mr -= T(h.re);
                         mi -= T(h.im);
                     }

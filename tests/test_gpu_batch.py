@@ -285,3 +285,26 @@ def test_autotune_keeps_results(gpu_lib):
         _check_jobs(jobs, ref, "caller order")
     for d in devs:
         d.close()
+
+
+def test_batch_long_23_tube_matches_oracle(gpu_lib):
+    """A 1600-ring (23,0) tube (ring size 23, the batch's largest) among short
+    devices, on a fixed sample of 3 contour and 4 real-axis nodes (the real nodes
+    are Gauss-Legendre nodes of the bias window, none at the lead's E = U_lead
+    edge-state pole), against the oracle."""
+    negf = gpu_lib
+    ps = small_batch(seed=13, n_dev=3) + [W.device_problem(N=1600, n=23, seed=77, n_c=3, n_r=4)]
+    ref = O.solve(ps[-1])
+    for prec, tol_q, tol_i in ((negf.FP64, 1e-10, 1e-10), (negf.FP32_BULK, 1e-5, 1e-5)):
+        devs = open_devices(negf, ps, [prec] * len(ps))
+        with negf.Workspace() as ws:
+            got = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        g = got[-1]
+        eq = rel(g.charge, ref["charge"])
+        ei = abs(g.current - ref["current"]) / abs(ref["current"])
+        say("long (23,0) N=1600 vs oracle", "fp64" if prec == negf.FP64 else "fp32", eq, ei, rel(g.T, ref["T"]))
+        assert eq < tol_q and ei < tol_i
+        if prec == negf.FP64:
+            assert rel(g.T, ref["T"]) < 1e-9
+        for d in devs:
+            d.close()
