@@ -539,7 +539,10 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                 }
             }
             store_need = std::max(store_need, used * cbs);
-            TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, rec, 2, 0, gpw, false, dyn));
+            // ring size 1: the column kernel runs a real node's recursions itself (no stores
+            // between checkpoints), so the recursion kernel covers the contour nodes only
+            TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, B == 1 ? cdg : rec, 2, 0,
+                           gpw, false, dyn));
             // ring size 1: 16 items per lane and unit (one unit claim and span search per 1024 items)
             TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0,
                            B == 1 ? negf::CDIAG1_ITEMS : gpw, true, 0));
@@ -590,8 +593,9 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         for (int r = 0; r < rounds; ++r) {
             launches.push_back(Launch{negf::KIND_COUNT, KT_FP64, gi, 0, 0, (int)nreal, 1, 0, nreal, 0, 3,
                                       r == rounds - 1 ? -cap64 : cap64, 1});
-            launches.push_back(
-                Launch{negf::KIND_RECUR64, KT_FP64, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0, 1});
+            if (B != 1)   // ring size 1: the column kernel recomputes the recursions itself
+                launches.push_back(
+                    Launch{negf::KIND_RECUR64, KT_FP64, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, gdyn64[gi], 2, 0, 1});
             launches.push_back(Launch{negf::KIND_COLUMN64, KT_FP64, gi, 0, 0, (int)nreal, 2, 0, 2 * nreal, 0, 2, 0, 1});
         }
     }

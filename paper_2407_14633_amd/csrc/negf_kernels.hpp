@@ -1004,53 +1004,227 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #ifndef NEGF_FP32_WMAX
 #define NEGF_FP32_WMAX 16.0
 #endif
-// One chain of k_column for ring size 1: W starts at G_{N-1,N-1} (right lead,
-// forward store slot 0) or G_00 (left lead, backward store slot N-1) and moves
-// by W <- -p_n W with p_n the stored x~/y~ of ring n; A_n = gamma |W_n|^2 with
-// gamma = i (Sigma - conj Sigma) = -2 Im Sigma of this lead, and at the far end
-// T = gamma_other gamma |W|^2.  The same output checks as the block form.
+// ------------------------------------------------- real nodes at ring size 1
+// One real-axis node of a scalar chain, whole (Algorithms 1-2 for 1 x 1 blocks),
+// in one lane and without recursion stores: the stores of the block form would
+// cost 2 x 16 bytes per ring written and read again, which bounds those kernels
+// by HBM.  Instead the recursion states are kept every K rings (checkpoints, in
+// the node's own store slots) and the K values a column step needs are
+// recomputed from the nearest checkpoint into registers:
+//   pass 1  forward recursion y_n, checkpoint y_{jK-1} (j >= 1); G_{N-1,N-1};
+//   pass 2  down the rings in segments of K: recompute the segment's y~ from its
+//           checkpoint, step the right-lead column W <- -y~_n W (A_R of every
+//           ring), and run the backward recursion x_n alongside, checkpointing
+//           x_{jK}; G_00 at the end, and T_LR from W = G_{0,N-1};
+//   pass 3  up the rings: recompute each segment's x~ from its checkpoint and
+//           step the left-lead column W <- -x~_n W (A_L); T_RL from G_{N-1,0}.
+// The step arithmetic is that of k_recur / k_column at ring size 1, so the
+// outputs are those of the store-based form; the recursion runs 4 steps per ring
+// instead of 2 and touches no store between checkpoints.
+constexpr int CHAIN1_K = 16;
+
 template <typename TS>
-__device__ __forceinline__ void column_scalar(const JobDesc& J, const cx<TS>* store, int lead, int e, int ir) {
-    const int N = J.N;
-    const double gl = -2.0 * gload(J.sigma + (size_t)e * 2 + lead).im;
-    const double go = -2.0 * gload(J.sigma + (size_t)e * 2 + (1 - lead)).im;
-    const cx<TS> w0 = gload(store + (lead ? 0 : N - 1));
-    double wr = (double)w0.re, wi = (double)w0.im;
-    double* aout = reinterpret_cast<double*>(J.a_diag) + ((size_t)ir * 2 + lead) * N;
-    double wmax = 0.0, amn = 0.0, amx = 0.0;
-    // the propagators of the next four rings are in flight while a ring is processed
-    const cx<TS> z0{TS(0), TS(0)};
-    auto prop = [&](int s) { return s < N - 1 ? gload(store + (lead ? N - 1 - s : s)) : z0; };
-    cx<TS> p1 = prop(0), p2 = prop(1), p3 = prop(2), p4 = prop(3);
-    for (int s = 0; s < N; ++s) {
-        const int n = lead ? N - 1 - s : s;
-        const cx<TS> p = p1;
-        p1 = p2;
-        p2 = p3;
-        p3 = p4;
-        p4 = prop(s + 4);
-        const double acc = gl * fma(wr, wr, wi * wi);
-        gstore_s(aout + n, acc);
-        wmax = fmax(wmax, fabs(wr) + fabs(wi));
-        amn = s == 0 ? acc : fmin(amn, acc);
-        amx = s == 0 ? acc : fmax(amx, acc);
-        if (s == N - 1) break;
-        const double pr = -(double)p.re, pi = -(double)p.im;
-        const double nr = fma(pr, wr, -(pi * wi)), ni = fma(pr, wi, pi * wr);
-        wr = nr;
-        wi = ni;
+struct Chain1 {
+    static constexpr bool kF32 = sizeof(TS) == 4;
+    const JobDesc& J;
+    int e, N, K;
+    cx<double> z;
+
+    // coupling h of ring block c (n -> n+1)
+    __device__ __forceinline__ cx<TS> coupling(int c) const {
+        const int base = gload_s(J.ell_map + c) * K;
+        TS hr = TS(0), hi = TS(0);
+        for (int t = 0; t < K; ++t) {
+            const cx<double> h = gload(J.cval + base + t);
+            hr += TS(h.re);
+            hi += TS(h.im);
+        }
+        return cx<TS>{hr, hi};
     }
-    const double tsum = go * gl * fma(wr, wr, wi * wi);
-    gstore_s((lead == 1 ? J.Tout : J.Trl) + ir, tsum);
-    gstore_s(J.amax + 2 * ir + lead, amx);
-    const bool bad_T = !(tsum >= -1e-6 && tsum <= 1.0 + 1e-6);
-    const bool bad_A = !(amn >= -1e-6 * fabs(amx)) || !(amx < 1e300);
+    // (a_n - state)^{-1}; FP32-bulk inverts the two rings with a lead self-energy in FP64
+    __device__ __forceinline__ cx<TS> inv(int n, double u, TS sr, TS si) const {
+        if (!kF32 || n == 0 || n == N - 1) {
+            const cx<double> a = scalar_a(J, e, n, u, z);
+            double qr, qi;
+            pivot_recip(a.re - (double)sr, a.im - (double)si, qr, qi);
+            return cx<TS>{TS(qr), TS(qi)};
+        }
+        TS mr = TS(z.re - u) - sr, mi = TS(z.im) - si;
+        if (!J.hdiag_zero) {
+            const cx<double> h = gload(J.hdiag + n);
+            mr -= TS(h.re);
+            mi -= TS(h.im);
+        }
+        TS ir, ii;
+        pivot_recip(mr, mi, ir, ii);
+        return cx<TS>{ir, ii};
+    }
+    // one recursion step from the inverse: t = inv p, next state = q t
+    // (dir 0: p = -h, q = -conj(h); dir 1: p = -conj(h), q = -h)
+    __device__ __forceinline__ static cx<TS> tilde(cx<TS> in, cx<TS> h, int dir) {
+        const TS pr = -h.re, pi = dir ? h.im : -h.im;
+        return cx<TS>{fma(in.re, pr, -(in.im * pi)), fma(in.re, pi, in.im * pr)};
+    }
+    __device__ __forceinline__ static cx<TS> next(cx<TS> t, cx<TS> h, int dir) {
+        const TS qr = -h.re, qi = dir ? -h.im : h.im;
+        return cx<TS>{fma(qr, t.re, -(qi * t.im)), fma(qr, t.im, qi * t.re)};
+    }
+};
+
+// W <- -p W in FP64
+__device__ __forceinline__ void col_step(double& wr, double& wi, double pre, double pim) {
+    const double pr = -pre, pi = -pim;
+    const double nr = fma(pr, wr, -(pi * wi)), ni = fma(pr, wi, pi * wr);
+    wr = nr;
+    wi = ni;
+}
+
+template <typename TS>
+__device__ __forceinline__ void chain_scalar(const JobDesc& J, cx<TS>* ckf, cx<TS>* ckb, int e, int ir) {
+    constexpr int KS = CHAIN1_K;
+    const int N = J.N;
+    const Chain1<TS> C{J, e, N, J.K, gload(J.z + e)};
+    const double gR = -2.0 * gload(J.sigma + (size_t)e * 2 + 1).im;
+    const double gL = -2.0 * gload(J.sigma + (size_t)e * 2 + 0).im;
+    double* aL = reinterpret_cast<double*>(J.a_diag) + ((size_t)ir * 2 + 0) * N;
+    double* aR = reinterpret_cast<double*>(J.a_diag) + ((size_t)ir * 2 + 1) * N;
+    cx<TS> y{TS(0), TS(0)};
+    // ---- pass 1: forward recursion (a segment's potentials and couplings loaded first)
+    cx<TS> gNN{TS(0), TS(0)};
+    const int nseg = (N + KS - 1) / KS;
+    for (int j = 0; j < nseg; ++j) {
+        const int lo = j * KS;
+        double uu[KS];
+        cx<TS> hh[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo + k;
+            uu[k] = n < N ? gload_s(J.U + n) : 0.0;
+            hh[k] = n < N - 1 ? C.coupling(n) : cx<TS>{TS(0), TS(0)};
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo + k;
+            if (n < N) {
+                if (k == KS - 1) gstore(ckf + j + 1, y);         // y_{jK-1}: checkpoint j + 1 (n = (j+1)K - 1)
+                const cx<TS> iv = C.inv(n, uu[k], y.re, y.im);
+                if (n == N - 1)
+                    gNN = iv;
+                else
+                    y = Chain1<TS>::next(Chain1<TS>::tilde(iv, hh[k], 0), hh[k], 0);
+            }
+        }
+    }
+    // ---- pass 2: right-lead column down the rings, backward recursion alongside
+    double wr = (double)gNN.re, wi = (double)gNN.im, wmR = 0.0, amnR = 0.0, amxR = 0.0;
+    cx<TS> x{TS(0), TS(0)}, g00{TS(0), TS(0)};
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int lo = j * KS;
+        // potentials of rings lo-1 .. lo+K-1 and couplings of blocks lo-1 .. lo+K-2
+        double uu[KS + 1];
+        cx<TS> hh[KS];
+#pragma unroll
+        for (int k = 0; k <= KS; ++k) {
+            const int n = lo - 1 + k;
+            uu[k] = n >= 0 && n < N ? gload_s(J.U + n) : 0.0;
+            if (k < KS) hh[k] = n >= 0 && n < N - 1 ? C.coupling(n) : cx<TS>{TS(0), TS(0)};
+        }
+        // y~_n for the rings of this segment (n >= 1): forward steps lo-1 .. lo+K-2
+        cx<TS> buf[KS];
+        cx<TS> ys = j == 0 ? cx<TS>{TS(0), TS(0)} : gload(ckf + j);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo - 1 + k;               // forward step n gives y~_{n+1} = buf[k]
+            if (n >= 0 && n < N - 1) {
+                const cx<TS> t = Chain1<TS>::tilde(C.inv(n, uu[k], ys.re, ys.im), hh[k], 0);
+                buf[k] = t;
+                ys = Chain1<TS>::next(t, hh[k], 0);
+            } else {
+                buf[k] = cx<TS>{TS(0), TS(0)};
+            }
+        }
+#pragma unroll
+        for (int k = KS - 1; k >= 0; --k) {
+            const int n = lo + k;
+            if (n < N) {
+                const double acc = gR * fma(wr, wr, wi * wi);
+                gstore_s(aR + n, acc);
+                wmR = fmax(wmR, fabs(wr) + fabs(wi));
+                amnR = n == N - 1 ? acc : fmin(amnR, acc);
+                amxR = n == N - 1 ? acc : fmax(amxR, acc);
+                // backward recursion at ring n (state x_n), checkpoint x_{jK}
+                if (k == 0 && n > 0) gstore(ckb + j, x);
+                const cx<TS> iv = C.inv(n, uu[k + 1], x.re, x.im);
+                if (n == 0) {
+                    g00 = iv;
+                } else {
+                    x = Chain1<TS>::next(Chain1<TS>::tilde(iv, hh[k], 1), hh[k], 1);   // block n-1
+                    col_step(wr, wi, (double)buf[k].re, (double)buf[k].im);
+                }
+            }
+        }
+    }
+    const double tLR = gL * gR * fma(wr, wr, wi * wi);
+    // ---- pass 3: left-lead column up the rings
+    wr = (double)g00.re;
+    wi = (double)g00.im;
+    double wmL = 0.0, amnL = 0.0, amxL = 0.0;
+    for (int j = 0; j < nseg; ++j) {
+        const int lo = j * KS;
+        const int top = min(lo + KS, N - 1);
+        // potentials of rings lo+1 .. lo+K and couplings of blocks lo .. lo+K-1
+        double uu[KS];
+        cx<TS> hh[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo + k + 1;
+            uu[k] = n <= top ? gload_s(J.U + n) : 0.0;
+            hh[k] = n <= top ? C.coupling(n - 1) : cx<TS>{TS(0), TS(0)};
+        }
+        // x~_n for the rings of this segment (n < N-1): backward steps top .. lo+1
+        cx<TS> buf[KS];
+        cx<TS> xs = top == N - 1 ? cx<TS>{TS(0), TS(0)} : gload(ckb + j + 1);
+#pragma unroll
+        for (int k = KS - 1; k >= 0; --k) {
+            const int n = lo + k + 1;               // backward step n gives x~_{n-1} = buf[k]
+            if (n <= top) {
+                const cx<TS> t = Chain1<TS>::tilde(C.inv(n, uu[k], xs.re, xs.im), hh[k], 1);
+                buf[k] = t;
+                xs = Chain1<TS>::next(t, hh[k], 1);
+            } else {
+                buf[k] = cx<TS>{TS(0), TS(0)};
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo + k;
+            if (n < N) {
+                const double acc = gL * fma(wr, wr, wi * wi);
+                gstore_s(aL + n, acc);
+                wmL = fmax(wmL, fabs(wr) + fabs(wi));
+                amnL = n == 0 ? acc : fmin(amnL, acc);
+                amxL = n == 0 ? acc : fmax(amxL, acc);
+                if (n < N - 1) col_step(wr, wi, (double)buf[k].re, (double)buf[k].im);
+            }
+        }
+    }
+    const double tRL = gR * gL * fma(wr, wr, wi * wi);
+    gstore_s(J.Tout + ir, tLR);
+    gstore_s(J.Trl + ir, tRL);
+    gstore_s(J.amax + 2 * ir + 0, amxL);
+    gstore_s(J.amax + 2 * ir + 1, amxR);
+    bool bad = false, big = false;
+    const double ts[2] = {tRL, tLR}, amn[2] = {amnL, amnR}, amx[2] = {amxL, amxR}, wm[2] = {wmL, wmR};
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+        bad = bad || !(ts[l] >= -1e-6 && ts[l] <= 1.0 + 1e-6) || !(amn[l] >= -1e-6 * fabs(amx[l])) ||
+              !(amx[l] < 1e300);
+        big = big || wm[l] * (fabs(C.z.re) + fabs(C.z.im) + J.hnorm) > NEGF_FP32_WMAX;
+    }
     if constexpr (sizeof(TS) == 4) {
-        const cx<double> z = gload(J.z + e);
-        const bool big_w = wmax * (fabs(z.re) + fabs(z.im) + J.hnorm) > NEGF_FP32_WMAX;
-        if (bad_T || bad_A || big_w) atomicOr(&J.status[e], (int)ST_FP64);
+        if (bad || big) atomicOr(&J.status[e], (int)ST_FP64);
     } else {
-        if (bad_T || bad_A) atomicOr(&J.status[e], (int)ST_BAD);
+        if (bad) atomicOr(&J.status[e], (int)ST_BAD);
     }
 }
 
@@ -1079,11 +1253,12 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         const int N = J.N;
         const int e = u.e0 + (act ? gi : 0);     // node index within the job (>= n_c)
         const int ir = e - J.n_c;                 // real-axis index
-        if constexpr (B == 1) {   // scalar chains: one chain per lane
-            if (act)
-                column_scalar<TS>(J, reinterpret_cast<const cx<TS>*>(lead ? S.store_f : S.store_b) + u.off +
-                                         (size_t)(u.i0 + gi) * N,
-                                  lead, e, ir);
+        if constexpr (B == 1) {   // scalar chains: a real node whole per lane (both leads, side 0)
+            if (act && lead == 0) {
+                const size_t o = u.off + (size_t)(u.i0 + gi) * N;
+                chain_scalar<TS>(J, reinterpret_cast<cx<TS>*>(S.store_f) + o, reinterpret_cast<cx<TS>*>(S.store_b) + o,
+                                 e, ir);
+            }
             continue;
         }
         wave_sync();
