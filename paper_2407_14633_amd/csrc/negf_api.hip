@@ -539,13 +539,14 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
                 }
             }
             store_need = std::max(store_need, used * cbs);
-            // ring size 1: the column kernel runs a real node's recursions itself (no stores
-            // between checkpoints), so the recursion kernel covers the contour nodes only
+            // ring size 1: the column kernel runs a real node's recursions itself and the
+            // recursion kernel a contour node's (both without stores between checkpoints),
+            // so the recursion launch covers the contour nodes only
             TRY(add_launch(g.f32 ? negf::KIND_RECUR32 : negf::KIND_RECUR64, KT_RECUR, gi, B == 1 ? cdg : rec, 2, 0,
                            gpw, false, dyn));
-            // ring size 1: 16 items per lane and unit (one unit claim and span search per 1024 items)
-            TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0,
-                           B == 1 ? negf::CDIAG1_ITEMS : gpw, true, 0));
+            if (B != 1)   // ring size 1: the recursion kernel writes the contour diagonals itself
+                TRY(add_launch(g.f32 ? negf::KIND_CDIAG32 : negf::KIND_CDIAG64, KT_CDIAG, gi, cdg, 1, 0, gpw, true,
+                               0));
             TRY(add_launch(g.f32 ? negf::KIND_COLUMN32 : negf::KIND_COLUMN64, KT_COLUMN, gi, col, 2, 0, gpw, false,
                            0));
             if (g.f32) gcol[gi].insert(gcol[gi].end(), col.begin(), col.end());

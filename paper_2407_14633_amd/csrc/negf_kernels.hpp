@@ -471,9 +471,6 @@ struct JobDesc {
 // each unit once per side (direction or lead).  Units are numbered span by
 // span: first[s] = units before span s, so unit w belongs to the span with
 // first[s] <= w < first[s+1], and within it side = local % sides.
-// k_cdiag items per unit at ring size 1 (16 per lane)
-constexpr int CDIAG1_ITEMS = 1024;
-
 struct Span {
     int job, e0, cnt, pad;
     long long off;            // store element offset of node e0 (recursion stores)
@@ -609,66 +606,9 @@ __device__ __forceinline__ cx<double> scalar_a(const JobDesc& J, int e, int n, d
     return cx<double>{re, im};
 }
 
-// One chain of k_recur for ring size 1 (the same quantities and store slots as
-// the block form): inv = (a_n - state)^{-1}; real nodes store t = inv p (the P
-// product, x~/y~), contour nodes the next state q t; the last ring stores
-// G_{N-1,N-1} (forward, slot 0) or G_00 (backward, slot N-1) for real nodes.
-// FP32-bulk: the two rings with a lead self-energy are inverted in FP64.
-template <typename T>
-__device__ __forceinline__ void recur_scalar(const JobDesc& J, int dir, int e, bool contour, cx<double> z,
-                                             cx<T>* store, const cx<T>* s_eval) {
-    constexpr bool kF32 = sizeof(T) == 4;
-    const int N = J.N, K = J.K;
-    T yr = T(0), yi = T(0);
-    double u_next = gload_s(J.U + (dir ? N - 1 : 0));
-    // coupling-table offset of the step's block, loaded a step ahead
-    int base_next = N > 1 ? gload_s(J.ell_map + (dir ? N - 2 : 0)) * K : 0;
-    for (int s = 0; s < N; ++s) {
-        const int n = dir ? N - 1 - s : s;
-        const bool last = (s == N - 1);
-        if (last && contour) break;
-        const double uu = u_next;
-        if (!last) u_next = gload_s(J.U + (dir ? N - 2 - s : s + 1));
-        const int base = base_next;
-        if (s + 2 < N) base_next = gload_s(J.ell_map + (dir ? N - 3 - s : s + 1)) * K;
-        T ir, ii;
-        if (!kF32 || s == 0 || last) {
-            const cx<double> a = scalar_a(J, e, n, uu, z);
-            const double mr = a.re - (double)yr, mi = a.im - (double)yi;
-            double qr, qi;
-            pivot_recip(mr, mi, qr, qi);
-            ir = T(qr);
-            ii = T(qi);
-        } else {
-            T mr = T(z.re - uu) - yr, mi = T(z.im) - yi;
-            if (!J.hdiag_zero) {
-                const cx<double> h = gload(J.hdiag + n);
-                mr -= T(h.re);
-                mi -= T(h.im);
-            }
-            pivot_recip(mr, mi, ir, ii);
-        }
-        if (last) {
-            gstore(store + (dir ? N - 1 : 0), cx<T>{ir, ii});
-            break;
-        }
-        const int slot = dir ? N - 2 - s : s + 1;
-        T hr = T(0), hi = T(0);
-        for (int t = 0; t < K; ++t) {
-            const cx<T> h = s_eval[base + t];
-            hr += h.re;
-            hi += h.im;
-        }
-        // P product: fwd p = -h, bwd p = -conj(h);  Q product: fwd q = -conj(h), bwd q = -h
-        const T pr = -hr, pi = dir ? hi : -hi;
-        const T tr = fma(ir, pr, -(ii * pi)), ti = fma(ir, pi, ii * pr);
-        if (!contour) gstore(store + slot, cx<T>{tr, ti});
-        const T qr = -hr, qi = dir ? -hi : hi;
-        yr = fma(qr, tr, -(qi * ti));
-        yi = fma(qr, ti, qi * tr);
-        if (contour) gstore(store + slot, cx<T>{yr, yi});
-    }
-}
+// a contour node of a scalar chain, whole (defined with the real-node form below)
+template <typename TS>
+__device__ __forceinline__ void chain_contour(const JobDesc& J, cx<TS>* ckf, int e);
 
 // ================================================================ k_recur ==
 // Chain = (node, direction).  Direction 0 (forward) runs the left-connected
@@ -749,10 +689,10 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         }
         const cx<double> z = gload(J.z + e);
         if constexpr (B == 1) {
-            // scalar chains (ring size 1, e.g. one mode of a mode-space tube): one chain
-            // per lane, state in registers, no exchange between lanes
-            if (act) recur_scalar<T>(J, dir, e, contour, z, store, s_eval);
-            wave_sync();
+            // scalar chains (ring size 1, e.g. one mode of a mode-space tube): this launch
+            // covers the contour nodes, each whole in one lane (side 0; real nodes run in
+            // the column kernel)
+            if (act && dir == 0) chain_contour<T>(J, store, e);
             continue;
         }
         double u_next = act ? gload_s(J.U + (size_t)(dir ? N - 1 : 0) * B + r) : 0.0;
@@ -875,54 +815,6 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         const int e = u.e0 + el;                 // node inside the job
         const int n = item - el * N;
         const size_t o_row = u.off + ((size_t)el * N + n) * B * B + (size_t)r * B;
-        if constexpr (B == 1) {   // scalar chains: CDIAG1_ITEMS / 64 items per lane, no exchange
-            constexpr int M = CDIAG1_ITEMS / 64;
-            const int N1 = N - 1;
-            cx<T> ys[M], xs[M];
-            double us[M];
-            int es[M], ns[M];
-            bool ok[M];
-            // every item's operands first, so that their loads are in flight together
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const int item = u.i0 + k * 64 + lane;
-                ok[k] = item < n_items && k * 64 < S.gpw;
-                const int el = ok[k] ? item / N : 0;
-                const int nn = ok[k] ? item - el * N : 0;
-                es[k] = u.e0 + el;
-                ns[k] = nn;
-                const size_t o = u.off + (size_t)el * N + nn;
-                const cx<T> zero{T(0), T(0)};
-                ys[k] = ok[k] && nn > 0 ? gload(reinterpret_cast<const cx<T>*>(S.store_f) + o) : zero;
-                xs[k] = ok[k] && nn < N1 ? gload(reinterpret_cast<const cx<T>*>(S.store_b) + o) : zero;
-                us[k] = ok[k] ? gload_s(J.U + nn) : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                if (!ok[k]) continue;
-                const int e = es[k], nn = ns[k];
-                const cx<double> z = gload(J.z + e);
-                cx<T>* out = reinterpret_cast<cx<T>*>(J.gr_diag) + (size_t)e * N + nn;
-                if (!kF32 || nn == 0 || nn == N1) {
-                    const cx<double> a = scalar_a(J, e, nn, us[k], z);
-                    double qr, qi;
-                    pivot_recip(a.re - (double)ys[k].re - (double)xs[k].re, a.im - (double)ys[k].im - (double)xs[k].im,
-                                qr, qi);
-                    gstore(out, cx<T>{T(qr), T(qi)});
-                } else {
-                    T mr = T(z.re - us[k]) - ys[k].re - xs[k].re, mi = T(z.im) - ys[k].im - xs[k].im;
-                    if (!J.hdiag_zero) {
-                        const cx<double> h = gload(J.hdiag + nn);
-                        mr -= T(h.re);
-                        mi -= T(h.im);
-                    }
-                    T qr, qi;
-                    pivot_recip(mr, mi, qr, qi);
-                    gstore(out, cx<T>{qr, qi});
-                }
-            }
-            continue;
-        }
         // FP32-bulk: the rings that carry a lead self-energy are inverted in FP64
         const bool bnd = kF32 && (n == 0 || n == N - 1);
         if constexpr (kF32) {
@@ -1225,6 +1117,91 @@ __device__ __forceinline__ void chain_scalar(const JobDesc& J, cx<TS>* ckf, cx<T
         if (bad || big) atomicOr(&J.status[e], (int)ST_FP64);
     } else {
         if (bad) atomicOr(&J.status[e], (int)ST_BAD);
+    }
+}
+
+// One contour node of a scalar chain, whole: diag G^R_nn = (a_n - x_n - y_n)^{-1}
+// (Algorithm 1) without recursion stores.  Pass 1 runs the forward recursion
+// and keeps y_{jK}; pass 2 walks down the rings in segments of K, recomputes the
+// segment's y_n from its checkpoint into registers and runs the backward
+// recursion x_n alongside, writing G_nn per ring.  Same arithmetic as k_recur
+// and k_cdiag at ring size 1.
+template <typename TS>
+__device__ __forceinline__ void chain_contour(const JobDesc& J, cx<TS>* ckf, int e) {
+    constexpr int KS = CHAIN1_K;
+    constexpr bool kF32 = sizeof(TS) == 4;
+    const int N = J.N;
+    const Chain1<TS> C{J, e, N, J.K, gload(J.z + e)};
+    cx<TS>* out = reinterpret_cast<cx<TS>*>(J.gr_diag) + (size_t)e * N;
+    const int nseg = (N + KS - 1) / KS;
+    // ---- pass 1: forward recursion, checkpoint y_{jK}
+    cx<TS> y{TS(0), TS(0)};
+    for (int j = 0; j < nseg; ++j) {
+        const int lo = j * KS;
+        double uu[KS];
+        cx<TS> hh[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo + k;
+            uu[k] = n < N - 1 ? gload_s(J.U + n) : 0.0;
+            hh[k] = n < N - 1 ? C.coupling(n) : cx<TS>{TS(0), TS(0)};
+        }
+        if (j > 0) gstore(ckf + j, y);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int n = lo + k;
+            if (n < N - 1) y = Chain1<TS>::next(Chain1<TS>::tilde(C.inv(n, uu[k], y.re, y.im), hh[k], 0), hh[k], 0);
+        }
+    }
+    // ---- pass 2: down the rings; y_n recomputed per segment, x_n alongside
+    cx<TS> x{TS(0), TS(0)};
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int lo = j * KS;
+        // potentials of rings lo .. lo+K-1, couplings of blocks lo-1 .. lo+K-2
+        double uu[KS];
+        cx<TS> hh[KS + 1];
+#pragma unroll
+        for (int k = 0; k <= KS; ++k) {
+            const int c = lo - 1 + k;
+            hh[k] = c >= 0 && c < N - 1 ? C.coupling(c) : cx<TS>{TS(0), TS(0)};
+            if (k < KS) uu[k] = lo + k < N ? gload_s(J.U + lo + k) : 0.0;
+        }
+        cx<TS> ys[KS];
+        ys[0] = j == 0 ? cx<TS>{TS(0), TS(0)} : gload(ckf + j);
+#pragma unroll
+        for (int k = 0; k + 1 < KS; ++k) {
+            const int n = lo + k;
+            ys[k + 1] = n < N - 1 ? Chain1<TS>::next(Chain1<TS>::tilde(C.inv(n, uu[k], ys[k].re, ys[k].im), hh[k + 1], 0),
+                                                     hh[k + 1], 0)
+                                  : ys[k];
+        }
+#pragma unroll
+        for (int k = KS - 1; k >= 0; --k) {
+            const int n = lo + k;
+            if (n < N) {
+                // G_nn = (a_n - x_n - y_n)^{-1}
+                cx<TS> g;
+                if (!kF32 || n == 0 || n == N - 1) {
+                    const cx<double> a = scalar_a(J, e, n, uu[k], C.z);
+                    double qr, qi;
+                    pivot_recip(a.re - (double)ys[k].re - (double)x.re, a.im - (double)ys[k].im - (double)x.im, qr, qi);
+                    g = cx<TS>{TS(qr), TS(qi)};
+                } else {
+                    TS mr = TS(C.z.re - uu[k]) - ys[k].re - x.re, mi = TS(C.z.im) - ys[k].im - x.im;
+                    if (!J.hdiag_zero) {
+                        const cx<double> h = gload(J.hdiag + n);
+                        mr -= TS(h.re);
+                        mi -= TS(h.im);
+                    }
+                    TS qr, qi;
+                    pivot_recip(mr, mi, qr, qi);
+                    g = cx<TS>{qr, qi};
+                }
+                gstore(out + n, g);
+                // backward recursion step at ring n (block n-1)
+                if (n > 0) x = Chain1<TS>::next(Chain1<TS>::tilde(C.inv(n, uu[k], x.re, x.im), hh[k], 1), hh[k], 1);
+            }
+        }
     }
 }
 
