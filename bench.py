@@ -380,6 +380,14 @@ def serving_sweep(n_req: int, rates, precision=None, etas=(1e-6, 1e-3)) -> dict:
             out["precision"] = runs[-1]["precision"]
         else:
             out[f"eta_{eta:g}"] = entry
+    # the same stream with FP64 NEGF at the highest rate: in mode space the scalar chains
+    # gain nothing from FP32, and the FP64 recomputation of the nodes the FP32 checks mark
+    # (a third of the current-carrying subbands' nodes) makes FP32-bulk the slower form
+    from paper_2407_14633_amd import negf
+    if precision is None or precision == negf.FP32_BULK:
+        r64 = run_serving(n_req, rates[-1], precision=negf.FP64, eta=etas[0])
+        log("serving", r64)
+        out["fp64_negf"] = r64
     return out
 
 

@@ -74,3 +74,29 @@ def test_non_circulant_device_is_refused(gpu_lib):
     with pytest.raises(negf.NegfError) as ei:
         negf.ModeSpace(dev)
     assert ei.value.status == negf.NEGF_EINVAL
+
+
+@pytest.mark.parametrize("n,N,amp", [(17, 400, 0.15), (10, 1500, 0.3)])
+def test_fp32_bulk_mode_chains_within_contract(gpu_lib, n, N, amp):
+    """FP32-bulk scalar mode chains (ring size 1) against the FP64 mode chains (equal to
+    the real-space oracle, tests above) on the full 512 + 1536 grid: 1e-5 on charge and
+    current.  Without the FP64 recomputation of the nodes the FP32 checks mark, the
+    (10,0) 1500-ring tube misses it (current off by ~2e-5 in the current-carrying
+    subbands)."""
+    negf = gpu_lib
+    dev = W.zigzag_cnt(n, N)
+    j = np.arange(N)
+    prof = amp * (np.tanh((j - N / 4) / 10) - np.tanh((j - 3 * N / 4) / 10))
+    bias = W.Bias(0.15, -0.15)
+    grid = W.nonequilibrium_grid(W.gershgorin_lower(dev, np.repeat(prof, n)) - 1.0, bias, 512, 1536)
+    with negf.ModeSpace(dev) as ms, negf.Workspace() as ws:
+        ms.set_potential(prof)
+        ref = ms.solve(ws, bias, grid)
+    with negf.ModeSpace(dev, precision=negf.FP32_BULK) as ms, negf.Workspace() as ws:
+        ms.set_potential(prof)
+        got = ms.solve(ws, bias, grid)
+        nodes = ws.fp64_nodes(n)
+    eq, ei = rel(got.charge, ref.charge), abs(got.current - ref.current) / abs(ref.current)
+    say(f"  ({n},0) N={N} FP32-bulk modes: charge {eq:.2e} current {ei:.2e} T {rel(got.T, ref.T):.2e}; "
+        f"FP64-recomputed nodes per mode {nodes}")
+    assert eq < 1e-5 and ei < 1e-5
