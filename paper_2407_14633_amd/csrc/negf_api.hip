@@ -686,6 +686,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         S.tol = g.tol;
         S.maxit = g.maxit;
         S.gpw = L.gpw;
+        S.lane_spans = (L.fp64 == 2 && g.L->B == 1 && L.kind == negf::KIND_COLUMN64) ? 1 : 0;
         int grid = persistent_grid(w, g.L->func[L.kind], L.dyn, L.units);
         if (L.kind == negf::KIND_DECIMATE && dec_grid_cap[L.group] > 0) grid = std::min(grid, dec_grid_cap[L.group]);
         ev_begin(w, s, &ev);

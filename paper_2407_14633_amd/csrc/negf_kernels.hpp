@@ -492,6 +492,8 @@ struct Sched {
     cx<double>* scratch;      // decimation state, per workgroup: G chains x 6 b x b blocks
     double tol;               // decimation tolerance
     int maxit;                // decimation step limit
+    int lane_spans;           // 1: every span is one node and a unit takes 64 of them, one per
+                              // lane (ring size 1, FP64 recomputation rounds)
 };
 
 struct Unit {
@@ -1220,6 +1222,27 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
     cx<T>* St = s_stage[gsafe];
     cx<T>* Gm = s_gam[gsafe];
 
+    if constexpr (B == 1) {
+        if (S.lane_spans) {
+            // the round's node list: node k = span k, taken 64 at a time; m nodes this round
+            // (the unit prefix holds two units per node)
+            const int m = S.first[S.n_spans] / 2;
+            for (;;) {
+                int w = 0;
+                if (threadIdx.x == 0) w = atomicAdd(S.counter, 1);
+                w = __builtin_amdgcn_readfirstlane(w);
+                if (w * 64 >= m) break;
+                const int k = w * 64 + lane;
+                if (k < m) {
+                    const Span sp = S.spans[k];
+                    const JobDesc& J = S.jobs[sp.job];
+                    chain_scalar<TS>(J, reinterpret_cast<cx<TS>*>(S.store_f) + sp.off,
+                                     reinterpret_cast<cx<TS>*>(S.store_b) + sp.off, sp.e0, sp.e0 - J.n_c);
+                }
+            }
+            return;
+        }
+    }
     Unit u;
     while (next_unit<G>(S, u)) {
         const JobDesc& J = S.jobs[u.job];
