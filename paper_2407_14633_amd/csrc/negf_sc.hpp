@@ -5,7 +5,9 @@
 //   1-D finite-difference Poisson along the axis with a coaxial gate:
 //     a (2 phi_j - phi_{j-1} - phi_{j+1}) + phi_j = V_GS - c (rho_in_j - n_ref_j)
 //     a = eps_1d / (c_gate dz^2),  c = e / (c_gate dz),  phi_{-1} = 0,  phi_N = V_DS
-//   U_{j,i} = -phi_j (eV) written into the device's potential.
+//   U_{j,i} = -phi_j (eV) written into the device's potential; the tridiagonal
+//   system is solved with its Thomas factors (computed once per request) by two
+//   workgroup-wide scans of the substitution recurrences.
 // Stopping norm: the relative charge change max_j |f_j| / (rho_in_j + rho_out_j)
 // of Algorithm 3, or the potential residual max_j |phi(rho_out)_j - phi(rho_in)_j|
 // (eV for one electron), which the linear Poisson operator gives as the solution
@@ -43,6 +45,9 @@ struct ScReq {
     double* Vt;               // [H+1][N] rows 1..H of V^T
     double* Wc;               // [H+1][N] columns 1..H of W
     double* work;             // [4N]
+    double* alf;              // [N] Thomas factors of the Poisson operator (set by mode 0):
+    double* invden;           // [N]   invden_j = 1 / (2a + 1 + a cp_{j-1}), alf_j = a invden_j,
+    double* mcp;              // [N]   mcp_j = -cp_j = a invden_j
     int* stat;                // [4]: m, passes, state (0 running, 1 converged, 2 pass limit)
     double* diag;             // [2]: eps_max of the last pass, |Delta f|^2
 };
@@ -74,6 +79,61 @@ __device__ __forceinline__ double sc_block_max(double v, double* red) {
     return red[0];
 }
 
+// x_j = alpha_j x_{j-1} + beta_j for j = 0..N-1 with x_{-1} = 0 (rev: j = N-1..0 with
+// x_N = 0), by the whole workgroup: every thread composes its chunk of steps into one
+// affine map, the maps are combined in thread order by a fixed Hillis-Steele scan,
+// and each chunk is re-run from the value it receives.  The order of operations
+// depends only on N, not on the other requests of the launch.
+__device__ __forceinline__ void sc_affine_scan(const double* alpha, const double* beta, double* x, int N, bool rev,
+                                               double* sA, double* sB) {
+    const int t = threadIdx.x;
+    const int C = (N + SC_THREADS - 1) / SC_THREADS;
+    const int lo = min(t * C, N), hi = min(lo + C, N);
+    __syncthreads();   // beta was written by other threads (strided, not in these chunks)
+    double A = 1.0, B = 0.0;
+    for (int q = lo; q < hi; ++q) {
+        const int j = rev ? N - 1 - q : q;
+        A = alpha[j] * A;
+        B = fma(alpha[j], B, beta[j]);
+    }
+    __syncthreads();
+    sA[t] = A;
+    sB[t] = B;
+    __syncthreads();
+    for (int o = 1; o < SC_THREADS; o <<= 1) {
+        double a2 = 1.0, b2 = 0.0;
+        if (t >= o) {
+            a2 = sA[t - o];
+            b2 = sB[t - o];
+        }
+        __syncthreads();
+        if (t >= o) {
+            const double a1 = sA[t], b1 = sB[t];
+            sA[t] = a1 * a2;
+            sB[t] = fma(a1, b2, b1);
+        }
+        __syncthreads();
+    }
+    double v = t > 0 ? sB[t - 1] : 0.0;
+    for (int q = lo; q < hi; ++q) {
+        const int j = rev ? N - 1 - q : q;
+        v = fma(alpha[j], v, beta[j]);
+        x[j] = v;
+    }
+    __syncthreads();
+}
+
+// Solves a (2 p_j - p_{j-1} - p_{j+1}) + p_j = rhs_j (p_{-1} = p_N = 0) with the
+// request's Thomas factors: forward dp_j = invden_j rhs_j + alf_j dp_{j-1}, then
+// p_j = dp_j + mcp_j p_{j+1}.  rhs is overwritten with invden_j rhs_j.
+__device__ __forceinline__ void sc_poisson(const ScReq& R, double* rhs, double* dp, double* out, double* sA,
+                                           double* sB) {
+    const int N = R.N;
+    for (int j = threadIdx.x; j < N; j += SC_THREADS) rhs[j] *= R.invden[j];
+    sc_affine_scan(R.alf, rhs, dp, N, false, sA, sB);
+    sc_affine_scan(R.mcp, dp, out, N, true, sA, sB);
+}
+
 // mode 0: start (rho_in = n_ref, empty history), then Poisson.
 // mode 1: one pass after a NEGF solve; Poisson unless the request has stopped.
 __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int mode) {
@@ -81,6 +141,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
     __shared__ double red[SC_THREADS];
     __shared__ double s_k[SC_MAX_HISTORY + 1];
     __shared__ double s_eps;
+    __shared__ double s_scanA[SC_THREADS], s_scanB[SC_THREADS];
     const int t = threadIdx.x, N = R.N;
     double* f = R.work;           // [N] f of this pass
     double* df = R.work + N;      // [N] Delta f
@@ -97,6 +158,16 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
             R.stat[2] = 0;
             R.diag[0] = 0.0;
             R.diag[1] = 0.0;
+            // Thomas factors of the constant Poisson matrix (once per request)
+            const double a = R.a, dg = 2.0 * a + 1.0;
+            double cprev = 0.0;
+            for (int j = 0; j < N; ++j) {
+                const double iv = 1.0 / (dg + a * cprev);   // sub-diagonal is -a
+                R.invden[j] = iv;
+                R.alf[j] = a * iv;
+                R.mcp[j] = a * iv;
+                cprev = -a * iv;
+            }
         }
     } else {
         if (R.stat[2] != 0) return;
@@ -114,32 +185,15 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
         }
         emax = sc_block_max(emax, red);
         const double d = sc_block_sum(dsum, red);
-        if (R.norm == 1) {                 // potential residual: Thomas sweep with right-hand side c f
+        if (R.norm == 1) {                 // potential residual: the Poisson operator on c f
+            double* rhs = R.work + 2 * N;
+            double* dp = R.work + 3 * N;
             __syncthreads();
-            if (t == 0) {
-                double* cp = R.work + 2 * N;
-                double* dp = R.work + 3 * N;
-                const double a = R.a, dg = 2.0 * a + 1.0;
-                double cprev = 0.0, dprev = 0.0;
-                for (int j = 0; j < N; ++j) {
-                    const double den = dg + a * cprev;
-                    const double cj = -a / den;
-                    const double dj = (R.c * f[j] + a * dprev) / den;
-                    cp[j] = cj;
-                    dp[j] = dj;
-                    cprev = cj;
-                    dprev = dj;
-                }
-                double next = 0.0, m = 0.0;
-                for (int j = N - 1; j >= 0; --j) {
-                    const double v = dp[j] - (j + 1 < N ? cp[j] * next : 0.0);
-                    next = v;
-                    m = nan_max(m, fabs(v));
-                }
-                s_eps = m;
-            }
-            __syncthreads();
-            emax = s_eps;
+            for (int j = t; j < N; j += SC_THREADS) rhs[j] = R.c * f[j];
+            sc_poisson(R, rhs, dp, rhs, s_scanA, s_scanB);
+            double m = 0.0;
+            for (int j = t; j < N; j += SC_THREADS) m = nan_max(m, fabs(rhs[j]));
+            emax = sc_block_max(m, red);
         }
         const int passes = R.stat[1] + 1;
         int m = R.stat[0];
@@ -202,33 +256,17 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
         }
         if (t == 0) R.stat[0] = m + 1;
     }
-    // Poisson: Thomas sweep on one lane (the matrix is diagonally dominant)
+    // Poisson: Thomas factors and two workgroup scans (the matrix is diagonally dominant)
     __syncthreads();
-    double* cp = R.work;             // [N] modified super-diagonal
-    double* dp = R.work + N;         // [N] modified right-hand side
+    double* rhs = R.work;            // [N] right-hand side
+    double* dp = R.work + N;         // [N] forward substitution
     double* phi = R.work + 2 * N;    // [N]
-    if (t == 0) {
-        const double a = R.a, diag = 2.0 * a + 1.0;
-        double cprev = 0.0, dprev = 0.0;
-        for (int j = 0; j < N; ++j) {
-            double rhs = R.V_GS - R.c * (R.rho_in[j] - R.n_ref[j]);
-            if (j == N - 1) rhs += a * R.V_DS;
-            const double den = diag + a * cprev;          // sub-diagonal is -a
-            const double cj = -a / den;
-            const double dj = (rhs + a * dprev) / den;
-            cp[j] = cj;
-            dp[j] = dj;
-            cprev = cj;
-            dprev = dj;
-        }
-        double next = 0.0;
-        for (int j = N - 1; j >= 0; --j) {
-            const double v = dp[j] - (j + 1 < N ? cp[j] * next : 0.0);
-            phi[j] = v;
-            next = v;
-        }
+    for (int j = t; j < N; j += SC_THREADS) {
+        double r = R.V_GS - R.c * (R.rho_in[j] - R.n_ref[j]);
+        if (j == N - 1) r += R.a * R.V_DS;
+        rhs[j] = r;
     }
-    __syncthreads();
+    sc_poisson(R, rhs, dp, phi, s_scanA, s_scanB);
     for (int u = 0; u < R.n_U; ++u) {
         double* Uu = R.U[u];
         const int w = R.U_w;

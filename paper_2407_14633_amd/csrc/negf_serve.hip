@@ -128,7 +128,7 @@ size_t estimate_footprint(const ScJob& j) {
     s += nc * 32 + nr * 16;                                            // grid
     s += Nb * 8 + (size_t)j.b * 16;                                    // outputs, potential pointers
     s += ne * 2 * (j.want_modes ? (size_t)j.b : b2) * 16;              // self-energy cache
-    s += (size_t)(9 + 2 * (j.H + 1)) * N * 8;                          // mixing state and Poisson scratch
+    s += (size_t)(12 + 2 * (j.H + 1)) * N * 8;                         // mixing state, Poisson factors and scratch
     s += nc * Nb * (f32 ? 8 : 16) + nr * 2 * Nb * 8;                   // per-node diagonals
     s += (size_t)32 * Nb * 8 + ne * (j.want_modes ? (size_t)j.b : 1) * 96;   // reduction partials, per-node scalars
     if (j.adaptive) s += nr * 16 * (j.want_modes ? (size_t)j.b : 1);  // grid probe at the capacity
@@ -164,7 +164,7 @@ negf_status setup(negf_server* S, ScJob* j) {
     const int nj = j->n_jobs();
     const size_t nc = j->z_c.size(), nr = j->n_r_cap, ne = j->ne_cap(), Nb = N * j->b;
     const size_t sig_per_node = j->modes ? (size_t)j->b : (size_t)j->b * j->b;   // 2 x this per node
-    const size_t n_state = 5 * N + 2 * (size_t)(j->H + 1) * N + 4 * N;
+    const size_t n_state = 5 * N + 2 * (size_t)(j->H + 1) * N + 4 * N + 3 * N;
     // eleven sub-arrays, each rounded up to 256 bytes
     const size_t bytes = nc * 32 + ne * 2 * sig_per_node * 16 + (2 * nr + Nb + nj + N + n_state) * 8 + nj * 8 +
                          11 * 256;
@@ -220,6 +220,9 @@ negf_status setup(negf_server* S, ScJob* j) {
     R.Vt = st + 5 * N;
     R.Wc = st + 5 * N + (size_t)(j->H + 1) * N;
     R.work = st + 5 * N + 2 * (size_t)(j->H + 1) * N;
+    R.alf = R.work + 4 * N;
+    R.invden = R.work + 5 * N;
+    R.mcp = R.work + 6 * N;
     R.stat = S->d_stat + 4 * j->slot;
     R.diag = S->d_diag + 2 * j->slot;
     return NEGF_OK;
