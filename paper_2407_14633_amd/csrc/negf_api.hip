@@ -655,9 +655,16 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
     ev_end(w, KT_REDUCE, s, ev);
 
     const negf::Span* cur_all = nullptr;   // node list of the group being recomputed
+    bool side_open = false;                 // a contour-diagonal launch on the side stream is not joined yet
     for (size_t li = 0; li < launches.size(); ++li) {
         const Launch& L = launches[li];
         const Group& g = groups[L.group];
+        const bool to_side = w->side && !L.fp64 && (L.kind == negf::KIND_CDIAG64 || L.kind == negf::KIND_CDIAG32);
+        const bool beside = !L.fp64 && (L.kind == negf::KIND_COLUMN64 || L.kind == negf::KIND_COLUMN32);
+        if (side_open && !beside) {   // nothing but the chunk's lead columns runs beside the diagonals
+            HIPCHK(hipStreamWaitEvent(s, w->ev_join, 0));
+            side_open = false;
+        }
         if (L.fp64 == 1) {   // list of the group's nodes to recompute; the cursor is reset
             int* ctl = d_fp64_ctl + 2 * L.group;
             hipLaunchKernelGGL(negf::k_fill_int, dim3(1), dim3(64), 0, s, ctl + 1, 1, 0);
@@ -689,10 +696,24 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         S.lane_spans = (L.fp64 == 2 && g.L->B == 1 && L.kind == negf::KIND_COLUMN64) ? 1 : 0;
         int grid = persistent_grid(w, g.L->func[L.kind], L.dyn, L.units);
         if (L.kind == negf::KIND_DECIMATE && dec_grid_cap[L.group] > 0) grid = std::min(grid, dec_grid_cap[L.group]);
-        ev_begin(w, s, &ev);
-        g.L->launch[L.kind](S, grid, L.dyn, s);
-        ev_end(w, L.kt, s, ev);
+        hipStream_t ls = s;
+        if (to_side) {   // fork: the side stream waits for the recursion of this chunk
+            HIPCHK(hipEventRecord(w->ev_fork, s));
+            HIPCHK(hipStreamWaitEvent(w->side, w->ev_fork, 0));
+            ls = w->side;
+        }
+        ev_begin(w, ls, &ev);
+        g.L->launch[L.kind](S, grid, L.dyn, ls);
+        ev_end(w, L.kt, ls, ev);
+        if (to_side) {
+            HIPCHK(hipEventRecord(w->ev_join, w->side));
+            side_open = true;
+        } else if (side_open) {   // the lead columns are queued: join behind them
+            HIPCHK(hipStreamWaitEvent(s, w->ev_join, 0));
+            side_open = false;
+        }
     }
+    if (side_open) HIPCHK(hipStreamWaitEvent(s, w->ev_join, 0));
 
     // ---- a6: weighted energy sums (status folded into the flags by k_coef)
     ev_begin(w, s, &ev);
@@ -779,7 +800,20 @@ negf_status ws_create(negf_workspace** out, size_t store_bytes) {
         delete w;
         return fail(NEGF_EHIP, "event creation failed");
     }
+    if (hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
+        if (w->side) (void)hipStreamDestroy(w->side);
+        (void)hipEventDestroy(w->done);
+        (void)hipStreamDestroy(w->own_stream);
+        delete w;
+        return fail(NEGF_EHIP, "side stream creation failed");
+    }
     if (hipHostMalloc((void**)&w->h_flags, kFlagInts * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipEventDestroy(w->ev_join);
+        (void)hipEventDestroy(w->ev_fork);
+        (void)hipStreamDestroy(w->side);
         (void)hipEventDestroy(w->done);
         (void)hipStreamDestroy(w->own_stream);
         delete w;
@@ -807,6 +841,9 @@ void ws_destroy(negf_workspace* w) {
         if (b->p) (void)hipFree(b->p);
     if (w->h_flags) (void)hipHostFree(w->h_flags);
     if (w->done) (void)hipEventDestroy(w->done);
+    if (w->ev_join) (void)hipEventDestroy(w->ev_join);
+    if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
+    if (w->side) (void)hipStreamDestroy(w->side);
     if (w->own_stream) (void)hipStreamDestroy(w->own_stream);
     delete w;
 }

@@ -80,6 +80,10 @@ struct negf_workspace {
     std::vector<int> last_max_iter;
     std::vector<int> last_fp64;      // per job of the last finished solve: nodes recomputed in FP64
     hipStream_t own_stream = nullptr;
+    // contour diagonals run on `side` beside the lead columns of the same chunk:
+    // forked after the recursion, joined before anything else touches the stores
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // profiling
     bool prof = false;
     struct Ev { int kind; hipEvent_t a, b; };

@@ -80,6 +80,9 @@ negf_status negf_solve_dev_static(negf_device* d, const negf_bias* bias, int n_c
     w.dev_id = own->dev_id;
     w.cus = own->cus;
     w.done = own->done;
+    w.side = own->side;
+    w.ev_fork = own->ev_fork;
+    w.ev_join = own->ev_join;
     w.h_flags = own->h_flags;
     w.cap_flags = own->cap_flags;
     w.grid_scale = own->grid_scale;
