@@ -48,6 +48,7 @@ typedef enum {
     NEGF_ESINGULAR = -4,  /* non-finite or impossible output (negative
                              spectral density, T_LR outside [0, b])      */
     NEGF_EHIP = -5,       /* HIP runtime error                             */
+    NEGF_ETIMEDOUT = -6,  /* serving: the request's deadline passed         */
     NEGF_PENDING = 1      /* negf_server_poll: the request has not finished */
 } negf_status;
 
@@ -440,17 +441,24 @@ typedef struct {
     double grid_l1, grid_l2;  /* guessed part limits of every rebuild (eV)                  */
     double grid_a, grid_b;    /* refinement E_l1 - a kT, E_s + b kT (the paper: 3, 1)       */
     int grid_refresh;         /* passes between rebuilds; 0 = 50                            */
+    const double *rho_init;   /* [n_rings] starting per-ring electron counts, e.g. the
+                                 converged rho of a neighbouring bias point (Section 3.3:
+                                 each bias point starts from the previous one); NULL: n_ref */
+    double deadline_ms;       /* > 0: the request ends with NEGF_ETIMEDOUT when it has not
+                                 finished this long after submission (queued or running;
+                                 a running one returns its last pass's charge and U)      */
 } negf_sc_request;
 
 typedef struct {
     int status;          /* NEGF_OK: converged; NEGF_ENOCONV: pass limit or decimation;
-                            other: solve or HIP error                                      */
+                            NEGF_ETIMEDOUT: deadline; other: solve or HIP error            */
     int iterations;      /* NEGF passes taken                                              */
     double eps_max;      /* stopping norm of the last pass                                 */
     double current;      /* A, at the last potential                                       */
     double t_queue_ms, t_run_ms, t_total_ms;   /* submit->admit, admit->done, submit->done */
     int n_r;             /* real-axis nodes of the last pass                               */
     int mode_space;      /* 1: the request ran as b scalar mode chains                     */
+    int evictions;       /* times the request was evicted to host state and re-admitted   */
 } negf_sc_result;
 
 typedef struct {
@@ -469,6 +477,20 @@ negf_status negf_server_poll(negf_server *s, long long id, int wait, negf_sc_res
                              double *charge, double *U, double *eps_trace);
 /* Queue and memory counters; returns the last fatal status of the server thread. */
 negf_status negf_server_stats(negf_server *s, negf_server_info *info);
+/* Eviction to host state and re-admission.  A running request can be evicted between
+ * passes: its mixing state (rho_in, the previous rho_in and f, s, the stored Broyden
+ * columns, pass counters), its current real-axis grid and its trace are copied to
+ * host memory, its device memory and slot are freed, and it is queued again at the
+ * back; when re-admitted it resumes from that state (the potential is rebuilt from
+ * rho_in, self-energies are decimated again), so its results are bit-identical to an
+ * uninterrupted run.  negf_server_evict(s, id) asks for one eviction (EINVAL if the
+ * request is unknown or finished; it takes effect at the end of the current pass if
+ * the request is running).  negf_server_set_time_slice(s, passes) makes the server
+ * evict, whenever requests are waiting for admission, every running request that has
+ * run `passes` passes since it was (re)admitted (0 = never, the default): round-robin
+ * service under overload. */
+negf_status negf_server_evict(negf_server *s, long long id);
+negf_status negf_server_set_time_slice(negf_server *s, int passes);
 /* Stops admitting, finishes the running requests, cancels the queued ones, frees all. */
 void negf_server_destroy(negf_server *s);
 

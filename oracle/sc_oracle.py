@@ -24,7 +24,9 @@ reduced to one dimension along the tube axis):
   Its maximum (V, i.e. eV for one electron) is the alternative stopping norm
   (norm = 1) that states the tolerance as a potential.
 * ``self_consistent``: the loop rho_in -> Poisson -> U -> NEGF (the FP64
-  oracle of ``negf_oracle``) -> rho_out -> Broyden, from rho_in = n_ref.  With
+  oracle of ``negf_oracle``) -> rho_out -> Broyden, from rho_in = n_ref, or from
+  a given starting charge (a warm start from a neighbouring bias point, as the
+  paper does along an I-V sweep, Section 3.3).  With
   a semi-adaptive grid (Section 3.3), the real-axis nodes are rebuilt by
   ``grid_oracle.semi_adaptive_grid`` at the current potential before NEGF pass
   1, 1 + refresh, 1 + 2 refresh, ... (reading: "refreshed every so many
@@ -139,7 +141,7 @@ def self_consistent(req, solve=None):
     from . import grid_oracle as G
     solve = solve or (lambda p: O.solve(p))
     b = req.device.b
-    br = Broyden(req.elec.n_ref, req.zeta, req.history)
+    br = Broyden(req.elec.n_ref if req.rho_init is None else req.rho_init, req.zeta, req.history)
     trace = []
     out = None
     grid = req.grid

@@ -38,6 +38,7 @@ struct ScReq {
     const double* charge;     // NEGF output of this pass
     double* const* U;         // [n_U] device potentials, each [N * U_w] (written)
     const double* n_ref;      // [N]
+    const double* rho0;       // [N] starting rho_in (n_ref, or a warm start)
     double* rho_in;           // [N]
     double* rho_in_old;       // [N]
     double* f_old;            // [N]
@@ -134,7 +135,8 @@ __device__ __forceinline__ void sc_poisson(const ScReq& R, double* rhs, double* 
     sc_affine_scan(R.mcp, dp, out, N, true, sA, sB);
 }
 
-// mode 0: start (rho_in = n_ref, empty history), then Poisson.
+// mode 0: start (rho_in = rho0, empty history), then Poisson.
+// mode 2: resume from a restored state (re-admission), Poisson only.
 // mode 1: one pass after a NEGF solve; Poisson unless the request has stopped.
 __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int mode) {
     const ScReq& R = reqs[blockIdx.x];
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
     double* df = R.work + N;      // [N] Delta f
     if (mode == 0) {
         for (int j = t; j < N; j += SC_THREADS) {
-            R.rho_in[j] = R.n_ref[j];
+            R.rho_in[j] = R.rho0[j];
             R.rho_in_old[j] = 0.0;
             R.f_old[j] = 0.0;
             R.s[j] = 0.0;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_sc_step(const ScReq* reqs, int m
                 cprev = -a * iv;
             }
         }
-    } else {
+    } else if (mode == 1) {
         if (R.stat[2] != 0) return;
         double emax = 0.0, dsum = 0.0;
         for (int j = t; j < N; j += SC_THREADS) {

@@ -78,6 +78,16 @@ struct ScJob {
     bool done = false;
     std::vector<double> charge_out, U_out;
     std::vector<double> trace;    // stopping norm of every pass
+    // warm start, deadline, eviction
+    std::vector<double> rho_init;  // [N] starting rho_in (empty: n_ref)
+    double deadline_ms = 0;
+    bool evict_req = false;        // evict at the end of the next pass (set under the lock)
+    bool resume = false;           // re-admission: restore the host state below
+    int evictions = 0, admitted_pass = 0;
+    std::vector<double> sv_state;  // saved at eviction: mixing state, Poisson factors and scratch
+    int sv_stat[4] = {0, 0, 0, 0};   // saved pass counters and state
+    double sv_diag[2] = {0, 0};
+    size_t n_state = 0;
 
     int n_jobs() const { return modes ? (int)modes->devs.size() : 1; }
     int ring_width() const { return modes ? 1 : b; }   // entries per ring of each NEGF job
@@ -108,6 +118,7 @@ struct negf_server {
     std::map<long long, ScJob*> jobs;
     long long next_id = 1;
     negf_status fatal = NEGF_OK;
+    int slice = 0;                // passes after which a running request yields to queued ones
     std::string fatal_msg;
     long long passes = 0;
 };
@@ -166,8 +177,9 @@ negf_status setup(negf_server* S, ScJob* j) {
     const size_t sig_per_node = j->modes ? (size_t)j->b : (size_t)j->b * j->b;   // 2 x this per node
     const size_t n_state = 5 * N + 2 * (size_t)(j->H + 1) * N + 4 * N + 3 * N;
     // eleven sub-arrays, each rounded up to 256 bytes
-    const size_t bytes = nc * 32 + ne * 2 * sig_per_node * 16 + (2 * nr + Nb + nj + N + n_state) * 8 + nj * 8 +
-                         11 * 256;
+    const size_t bytes = nc * 32 + ne * 2 * sig_per_node * 16 + (2 * nr + Nb + nj + 2 * N + n_state) * 8 + nj * 8 +
+                         12 * 256;
+    j->n_state = n_state;
     HIPCHK(hipMalloc(&j->mem, bytes));
     char* p = static_cast<char*>(j->mem);
     auto take = [&](size_t n) { char* q = p; p += (n + 255) & ~size_t(255); return q; };
@@ -179,6 +191,7 @@ negf_status setup(negf_server* S, ScJob* j) {
     j->d_charge = reinterpret_cast<double*>(take(Nb * 8));
     j->d_cur = reinterpret_cast<double*>(take(nj * 8));
     j->d_nref = reinterpret_cast<double*>(take(N * 8));
+    double* d_rho0 = reinterpret_cast<double*>(take(N * 8));
     j->d_state = reinterpret_cast<double*>(take(n_state * 8));
     j->d_Uptr = reinterpret_cast<double**>(take(nj * 8));
     if (nc) {
@@ -190,6 +203,12 @@ negf_status setup(negf_server* S, ScJob* j) {
         HIPCHK(hipMemcpy(j->d_wr, j->w_r.data(), (size_t)j->n_r * 8, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemcpy(j->d_nref, j->n_ref.data(), N * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_rho0, (j->rho_init.empty() ? j->n_ref : j->rho_init).data(), N * 8, hipMemcpyHostToDevice));
+    if (j->resume) {   // re-admission: the mixing state as it was when the request was evicted
+        HIPCHK(hipMemcpy(j->d_state, j->sv_state.data(), n_state * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S->d_stat + 4 * j->slot, j->sv_stat, 4 * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S->d_diag + 2 * j->slot, j->sv_diag, 2 * sizeof(double), hipMemcpyHostToDevice));
+    }
     std::vector<double*> uptr(nj);
     for (int k = 0; k < nj; ++k) uptr[k] = j->modes ? j->modes->devs[k]->d_U : j->dev->d_U;
     HIPCHK(hipMemcpy(j->d_Uptr, uptr.data(), nj * 8, hipMemcpyHostToDevice));
@@ -212,6 +231,7 @@ negf_status setup(negf_server* S, ScJob* j) {
     R.charge = j->d_charge;
     R.U = j->d_Uptr;
     R.n_ref = j->d_nref;
+    R.rho0 = d_rho0;
     double* st = j->d_state;
     R.rho_in = st;
     R.rho_in_old = st + N;
@@ -326,6 +346,8 @@ negf_status refresh_grid(negf_server* S, ScJob* j) {
     HIPCHK(hipMemcpy(j->d_Er, Ef.data(), Ef.size() * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(j->d_wr, Wf.data(), Wf.size() * 8, hipMemcpyHostToDevice));
     j->n_r = (int)Ef.size();
+    j->E_r = Ef;   // host copy: a re-admitted request resumes on this grid
+    j->w_r = Wf;
     j->sigma_ready = false;      // the real-axis nodes moved: decimate again
     return NEGF_OK;
 }
@@ -371,12 +393,32 @@ void finish_job(negf_server* S, ScJob* j, int status) {
     S->cv_done.notify_all();
 }
 
+// Moves a running request's state to host memory, frees its device memory and slot,
+// and queues it again at the back (the caller has taken it out of the running set).
+negf_status evict_job(negf_server* S, ScJob* j) {
+    j->sv_state.resize(j->n_state);
+    HIPCHK(hipMemcpy(j->sv_state.data(), j->d_state, j->n_state * 8, hipMemcpyDeviceToHost));
+    for (int k = 0; k < 4; ++k) j->sv_stat[k] = S->h_stat[4 * j->slot + k];
+    for (int k = 0; k < 2; ++k) j->sv_diag[k] = S->h_diag[2 * j->slot + k];
+    release(j);
+    j->resume = true;
+    j->sigma_ready = false;
+    j->evictions++;
+    std::lock_guard<std::mutex> lk(S->mu);
+    j->evict_req = false;
+    S->free_slots.push_back(j->slot);
+    j->slot = -1;
+    S->used -= std::min(S->used, j->footprint);
+    S->pending.push_back(j);
+    return NEGF_OK;
+}
+
 // one pass over the running set; returns a non-OK status only for errors that stop the server
 negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
     // set up the newly admitted requests and start their mixing state
     std::vector<ScJob*> fresh;
     for (ScJob* j : admitted) {
-        j->t_admit = now_ms();
+        if (j->t_admit == 0) j->t_admit = now_ms();
         const negf_status st = setup(S, j);
         if (st != NEGF_OK) {
             finish_job(S, j, st);
@@ -386,15 +428,27 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
     }
     admitted.clear();
     if (!fresh.empty()) {
-        std::vector<negf::ScReq> rq;
-        for (ScJob* j : fresh) rq.push_back(j->rq);
-        HIPCHK(hipMemcpy(S->d_reqs, rq.data(), rq.size() * sizeof(negf::ScReq), hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(negf::k_sc_step, dim3((unsigned)fresh.size()), dim3(negf::SC_THREADS), 0, S->stream,
-                           S->d_reqs, 0);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(S->stream));
+        // new requests start their mixing state (mode 0); re-admitted ones rebuild their
+        // potential from the restored state (mode 2)
+        for (int mode : {0, 2}) {
+            std::vector<negf::ScReq> rq;
+            for (ScJob* j : fresh)
+                if (j->resume == (mode == 2)) rq.push_back(j->rq);
+            if (rq.empty()) continue;
+            HIPCHK(hipMemcpy(S->d_reqs, rq.data(), rq.size() * sizeof(negf::ScReq), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(negf::k_sc_step, dim3((unsigned)rq.size()), dim3(negf::SC_THREADS), 0, S->stream,
+                               S->d_reqs, mode);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(S->stream));
+        }
         std::lock_guard<std::mutex> lk(S->mu);   // negf_server_stats reads the running set
-        for (ScJob* j : fresh) S->running.push_back(j);
+        for (ScJob* j : fresh) {
+            j->resume = false;
+            j->sv_state.clear();
+            j->sv_state.shrink_to_fit();
+            j->admitted_pass = j->passes;
+            S->running.push_back(j);
+        }
     }
     if (S->running.empty()) return NEGF_OK;
 
@@ -442,7 +496,13 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
         S->passes++;
     }
     // per-request NEGF flags (ST_NOCONV: decimation; ST_BAD / ST_NOROOM: bad result)
-    std::vector<ScJob*> keep;
+    std::vector<ScJob*> keep, evict;
+    bool waiting;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        waiting = !S->pending.empty();
+    }
+    const double t_now = now_ms();
     for (size_t r = 0; r < S->running.size(); ++r) {
         ScJob* j = S->running[r];
         j->sigma_ready = true;
@@ -452,12 +512,21 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
         j->passes = st[1];
         j->eps_max = S->h_diag[2 * j->slot];
         j->trace.push_back(j->eps_max);
+        bool ask;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            ask = j->evict_req;
+        }
         if (fl) {
             finish_job(S, j, (fl & negf::ST_NOCONV) ? NEGF_ENOCONV : NEGF_ESINGULAR);
         } else if (st[2] == 1) {
             finish_job(S, j, NEGF_OK);
         } else if (st[2] == 2) {
             finish_job(S, j, NEGF_ENOCONV);
+        } else if (j->deadline_ms > 0 && t_now - j->t_submit > j->deadline_ms) {
+            finish_job(S, j, NEGF_ETIMEDOUT);
+        } else if (ask || (S->slice > 0 && waiting && j->passes - j->admitted_pass >= S->slice)) {
+            evict.push_back(j);
         } else {
             keep.push_back(j);
         }
@@ -465,6 +534,10 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->running.swap(keep);
+    }
+    for (ScJob* j : evict) {
+        const negf_status st = evict_job(S, j);
+        if (st != NEGF_OK) finish_job(S, j, st);
     }
     S->ws->last_n_jobs = 0;
     return NEGF_OK;
@@ -486,6 +559,22 @@ void server_loop(negf_server* S) {
                 S->cv_done.notify_all();
                 return;
             }
+            // queued requests whose deadline passed end here (no device state to return)
+            const double tn = now_ms();
+            bool expired = false;
+            for (auto it = S->pending.begin(); it != S->pending.end();) {
+                ScJob* j = *it;
+                if (j->deadline_ms > 0 && tn - j->t_submit > j->deadline_ms) {
+                    j->status = NEGF_ETIMEDOUT;
+                    j->t_done = tn;
+                    j->done = true;
+                    it = S->pending.erase(it);
+                    expired = true;
+                } else {
+                    ++it;
+                }
+            }
+            if (expired) S->cv_done.notify_all();
             while (!S->stop && !S->pending.empty() && (int)(S->running.size() + admitted.size()) < S->max_inflight) {
                 ScJob* j = S->pending.front();
                 if (S->used + j->footprint > S->budget && !(S->running.empty() && admitted.empty())) break;
@@ -562,6 +651,10 @@ negf_status negf_server_submit(negf_server* S, const negf_sc_request* r, long lo
     if (!r->h_diag || !r->h_up || !r->left || !r->right || !r->n_ref)
         return fail(NEGF_EINVAL, "request has a NULL array");
     if (r->basis < 0 || r->basis > 1) return fail(NEGF_EINVAL, "basis %d not 0 or 1", r->basis);
+    if (!(r->deadline_ms >= 0) || !std::isfinite(r->deadline_ms)) return fail(NEGF_EINVAL, "deadline not >= 0");
+    if (r->rho_init)
+        for (int k = 0; k < r->n_rings; ++k)
+            if (!std::isfinite(r->rho_init[k])) return fail(NEGF_EINVAL, "rho_init[%d] not finite", k);
     if (r->norm < 0 || r->norm > 1) return fail(NEGF_EINVAL, "norm %d not 0 or 1", r->norm);
     const bool adaptive = r->grid_density[0] != 0 || r->grid_density[1] != 0 || r->grid_density[2] != 0;
     if (adaptive) {
@@ -633,6 +726,8 @@ negf_status negf_server_submit(negf_server* S, const negf_sc_request* r, long lo
         j->n_r = j->n_r_cap = r->n_r;
     }
     j->norm = r->norm;
+    if (r->rho_init) j->rho_init.assign(r->rho_init, r->rho_init + N);
+    j->deadline_ms = r->deadline_ms;
     if (r->basis == 0) {   // mode space when every block is ring-circulant (the potential always is ring-uniform)
         bool circ = true;
         for (int k = 0; k < N && circ; ++k) circ = ring_circulant(r->h_diag + (size_t)k * b2, b);
@@ -693,12 +788,31 @@ negf_status negf_server_poll(negf_server* S, long long id, int wait, negf_sc_res
         res->t_total_ms = j->t_done - j->t_submit;
         res->n_r = j->n_r;
         res->mode_space = j->want_modes ? 1 : 0;
+        res->evictions = j->evictions;
     }
     if (charge && !j->charge_out.empty()) memcpy(charge, j->charge_out.data(), j->charge_out.size() * 8);
     if (U && !j->U_out.empty()) memcpy(U, j->U_out.data(), j->U_out.size() * 8);
     if (eps_trace && !j->trace.empty()) memcpy(eps_trace, j->trace.data(), j->trace.size() * 8);
     S->jobs.erase(it);
     delete j;
+    return NEGF_OK;
+}
+
+negf_status negf_server_evict(negf_server* S, long long id) {
+    if (!S) return fail(NEGF_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    if (it == S->jobs.end()) return fail(NEGF_EINVAL, "unknown request %lld", id);
+    if (it->second->done) return fail(NEGF_EINVAL, "request %lld has finished", id);
+    it->second->evict_req = true;
+    return NEGF_OK;
+}
+
+negf_status negf_server_set_time_slice(negf_server* S, int passes) {
+    if (!S) return fail(NEGF_EINVAL, "server is NULL");
+    if (passes < 0) return fail(NEGF_EINVAL, "time slice %d < 0", passes);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->slice = passes;
     return NEGF_OK;
 }
 

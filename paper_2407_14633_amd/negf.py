@@ -18,10 +18,11 @@ from .workload import Bias, Device, EnergyGrid, Lead, Problem
 LIB_PATH = os.environ.get("NEGF_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnegf.so")
 
 NEGF_OK, NEGF_EINVAL, NEGF_ENOMEM, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_EHIP = 0, -1, -2, -3, -4, -5
+NEGF_ETIMEDOUT = -6
 NEGF_PENDING = 1
 FP64, FP32_BULK = 0, 1
 STATUS_NAMES = {0: "NEGF_OK", -1: "NEGF_EINVAL", -2: "NEGF_ENOMEM", -3: "NEGF_ENOCONV",
-                -4: "NEGF_ESINGULAR", -5: "NEGF_EHIP", 1: "NEGF_PENDING"}
+                -4: "NEGF_ESINGULAR", -5: "NEGF_EHIP", -6: "NEGF_ETIMEDOUT", 1: "NEGF_PENDING"}
 
 EXPORTED = [
     "negf_default_options", "negf_create_device", "negf_set_potential", "negf_set_potential_dev",
@@ -35,6 +36,7 @@ EXPORTED = [
     "negf_modes_set_potential", "negf_modes_solve", "negf_modes_destroy", "negf_semi_adaptive_grid",
     "negf_solve_dev_static", "negf_static_scratch_bytes", "negf_fp64_nodes", "negf_workspace_fp64_nodes",
     "negf_set_fp64_recompute", "negf_workspace_set_fp64_recompute", "negf_workspace_set_chains_per_wave",
+    "negf_server_evict", "negf_server_set_time_slice",
 ]
 
 
@@ -89,13 +91,13 @@ class negf_sc_request(C.Structure):
                 ("n_ref", C.c_void_p), ("zeta", C.c_double), ("tol", C.c_double), ("history", C.c_int),
                 ("max_iter", C.c_int), ("basis", C.c_int), ("norm", C.c_int), ("grid_density", C.c_double * 3),
                 ("grid_l1", C.c_double), ("grid_l2", C.c_double), ("grid_a", C.c_double), ("grid_b", C.c_double),
-                ("grid_refresh", C.c_int)]
+                ("grid_refresh", C.c_int), ("rho_init", C.c_void_p), ("deadline_ms", C.c_double)]
 
 
 class negf_sc_result(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("eps_max", C.c_double), ("current", C.c_double),
                 ("t_queue_ms", C.c_double), ("t_run_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("n_r", C.c_int), ("mode_space", C.c_int)]
+                ("n_r", C.c_int), ("mode_space", C.c_int), ("evictions", C.c_int)]
 
 
 class negf_server_info(C.Structure):
@@ -125,6 +127,10 @@ def load(path: str = LIB_PATH):
     lib.negf_solve_ex.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, C.POINTER(negf_outputs)]
     lib.negf_solve_dev.argtypes = [vp, C.POINTER(negf_bias), i, vp, vp, i, vp, vp, vp, vp, vp, vp]
     lib.negf_sync.argtypes = [vp]
+    lib.negf_server_evict.argtypes = [vp, C.c_longlong]
+    lib.negf_server_evict.restype = C.c_int
+    lib.negf_server_set_time_slice.argtypes = [vp, i]
+    lib.negf_server_set_time_slice.restype = C.c_int
     lib.negf_workspace_set_chains_per_wave.argtypes = [vp, i, i]
     lib.negf_workspace_set_chains_per_wave.restype = C.c_int
     lib.negf_set_fp64_recompute.argtypes = [vp, i]
@@ -614,6 +620,9 @@ class Server:
             r.grid_l1, r.grid_l2 = (float(v) for v in req.grid_limits)
             r.grid_a, r.grid_b = float(req.grid_a), float(req.grid_b)
             r.grid_refresh = int(req.grid_refresh)
+        if req.rho_init is not None:
+            r.rho_init = arr(np.asarray(req.rho_init, np.float64), np.float64)
+        r.deadline_ms = float(req.deadline_ms)
         rid = C.c_longlong()
         _check(load().negf_server_submit(self.h, C.byref(r), C.byref(rid)))
         self._sizes[rid.value] = (dev.n_rings * dev.b, req.max_iter)
@@ -633,7 +642,17 @@ class Server:
         self._sizes.pop(rid, None)
         return dict(status=res.status, iterations=res.iterations, eps_max=res.eps_max, current=res.current,
                     t_queue_ms=res.t_queue_ms, t_run_ms=res.t_run_ms, t_total_ms=res.t_total_ms, charge=charge,
-                    U=U, trace=tr[:res.iterations].copy(), n_r=res.n_r, mode_space=bool(res.mode_space))
+                    U=U, trace=tr[:res.iterations].copy(), n_r=res.n_r, mode_space=bool(res.mode_space),
+                    evictions=res.evictions)
+
+    def evict(self, rid: int):
+        """Evicts request rid to host state at the end of its next pass; it is queued again
+        and resumes from that state (results bit-identical to an uninterrupted run)."""
+        _check(load().negf_server_evict(self.h, C.c_longlong(rid)))
+
+    def set_time_slice(self, passes: int):
+        """Evict running requests after this many passes while others wait (0: never)."""
+        _check(load().negf_server_set_time_slice(self.h, int(passes)))
 
     def stats(self) -> dict:
         info = negf_server_info()

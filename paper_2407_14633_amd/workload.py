@@ -387,6 +387,8 @@ class ScRequest:
     grid_a: float = 3.0
     grid_b: float = 1.0
     grid_refresh: int = 50    # NEGF passes between rebuilds (the first before pass 1)
+    rho_init: Optional[np.ndarray] = None  # (N,) starting per-ring electron counts (warm start); None: n_ref
+    deadline_ms: float = 0.0  # > 0: the server ends the request after this long (NEGF_ETIMEDOUT)
     meta: dict = field(default_factory=dict)
 
     @property

@@ -173,6 +173,8 @@ def test_server_rejects_null(lib):
     assert lib.negf_server_submit(None, None, C.byref(rid)) == NG.NEGF_EINVAL
     assert lib.negf_server_poll(None, 1, 0, None, None, None, None) == NG.NEGF_EINVAL
     assert lib.negf_server_stats(None, None) == NG.NEGF_EINVAL
+    assert lib.negf_server_evict(None, 1) == NG.NEGF_EINVAL
+    assert lib.negf_server_set_time_slice(None, 2) == NG.NEGF_EINVAL
 
 
 def test_modes_and_grid_reject_bad_arguments(lib):

@@ -179,3 +179,71 @@ def test_server_rejects_bad_requests(gpu_lib):
         assert ei.value.status == negf.NEGF_EINVAL
         with pytest.raises(negf.NegfError):
             srv.poll(12345)
+
+
+def test_server_warm_start_matches_oracle(gpu_lib):
+    # a bias point started from the converged charge of its neighbour (an I-V sweep)
+    negf = gpu_lib
+    first = small_request(10, 30, 0.30, 0.1)
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        a = srv.poll(srv.submit(first))
+    rho = a["charge"].reshape(30, 10).sum(axis=1)
+    nxt = replace(small_request(10, 30, 0.35, 0.1), rho_init=rho)
+    cold = small_request(10, 30, 0.35, 0.1)
+    ref = S.self_consistent(nxt)
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        got = srv.poll(srv.submit(nxt))
+        c = srv.poll(srv.submit(cold))
+    dU = np.max(np.abs(got["U"] - ref["U"]))
+    say("warm passes gpu/oracle", got["iterations"], ref["iterations"], "cold", c["iterations"], "dU", dU,
+        "first-pass norm warm/cold", got["trace"][0], c["trace"][0])
+    assert got["status"] == negf.NEGF_OK and ref["converged"]
+    assert got["iterations"] == ref["iterations"] and dU < 1e-9
+    # the neighbour's charge is a better start: smaller first residual, no more passes
+    assert got["trace"][0] < 0.5 * c["trace"][0] and got["iterations"] <= c["iterations"]
+
+
+def _same(a, b):
+    return (a["status"] == b["status"] and a["iterations"] == b["iterations"] and np.array_equal(a["U"], b["U"])
+            and np.array_equal(a["charge"], b["charge"]) and a["current"] == b["current"]
+            and np.array_equal(a["trace"], b["trace"]))
+
+
+def test_server_eviction_resumes_bitwise(gpu_lib):
+    # one slot and a time slice of two passes: the requests take turns, each evicted to
+    # host state and re-admitted several times; every result equals its solo run
+    negf = gpu_lib
+    reqs = [small_request(10, 26, 0.3, 0.1, tol=1e-9),
+            small_request(8, 30, 0.2, -0.2, n_r=0, eta=1e-6, norm=1, tol=1e-9, grid_density=(2.0, 10.0, 4.0),
+                          grid_limits=(-0.2, 0.0), grid_refresh=3)]
+    solo = []
+    for r in reqs:
+        with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+            solo.append(srv.poll(srv.submit(r)))
+    with negf.Server(64 * GIB, max_inflight=1, store_bytes=GIB) as srv:
+        srv.set_time_slice(2)
+        ids = [srv.submit(r) for r in reqs]
+        got = [srv.poll(i) for i in ids]
+    say("evictions", [g["evictions"] for g in got], "passes", [g["iterations"] for g in got])
+    assert all(g["evictions"] >= 1 for g in got)
+    for s_, g in zip(solo, got):
+        assert s_["status"] == negf.NEGF_OK and _same(s_, g)
+
+
+def test_server_explicit_evict_and_deadline(gpu_lib):
+    negf = gpu_lib
+    req = small_request(10, 30, 0.4, -0.3, tol=1e-9)
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        base = srv.poll(srv.submit(req))
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        rid = srv.submit(req)
+        srv.evict(rid)                       # takes effect at the end of its first pass
+        got = srv.poll(rid)
+        with pytest.raises(negf.NegfError):
+            srv.evict(rid)                   # finished and released
+    say("explicit eviction: evictions", got["evictions"], "passes", got["iterations"], base["iterations"])
+    assert got["evictions"] == 1 and _same(base, got)
+    # a deadline far shorter than one pass: the request ends with ETIMEDOUT
+    with negf.Server(64 * GIB, store_bytes=GIB) as srv:
+        late = srv.poll(srv.submit(replace(req, deadline_ms=1e-3)))
+    assert late["status"] == negf.NEGF_ETIMEDOUT

@@ -156,3 +156,14 @@ def test_grid_rebuild_happens_before_the_first_pass():
     a, b = S.self_consistent(req), S.self_consistent(fixed)
     assert a["n_r"] == len(E_r) and a["iterations"] == b["iterations"]
     assert np.array_equal(a["U"], b["U"]) and a["trace"] == b["trace"]
+
+
+def test_warm_start_from_the_fixed_point_stops_at_once():
+    # starting from the converged rho_in reproduces that pass exactly: one pass, same U
+    from dataclasses import replace
+    req = W.sc_request(8, 12, 0.3, 0.2, n_c=8, n_r=12, tol=1e-8)
+    cold = S.self_consistent(req)
+    assert cold["converged"] and cold["iterations"] > 1
+    warm = S.self_consistent(replace(req, rho_init=cold["rho_in"]))
+    assert warm["iterations"] == 1 and warm["converged"]
+    assert np.array_equal(warm["U"], cold["U"]) and warm["eps_max"] == cold["eps_max"]
