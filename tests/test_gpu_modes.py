@@ -62,9 +62,14 @@ def test_modes_match_real_space_gpu_at_device_scale(gpu_lib):
         two.close()
     dI = abs(got.current - real.current) / abs(real.current)
     dI2 = abs(low.current - real.current) / abs(real.current)
+    # and against the oracle directly, on the same node sample
+    ref = O.solve(W.Problem("ms400", dev, U, 0.0, 0.0, bias, grid))
+    dIo = abs(got.current - ref["current"]) / abs(ref["current"])
     say(f"  (17,0) N=400 all modes: charge {rel(got.charge, real.charge):.2e} current {dI:.2e}; "
-        f"two lowest modes: current {dI2:.2e}")
+        f"two lowest modes: current {dI2:.2e}; vs oracle: charge {rel(got.charge, ref['charge']):.2e} "
+        f"T {rel(got.T, ref['T']):.2e} current {dIo:.2e}")
     assert rel(got.charge, real.charge) < 1e-10 and dI < 1e-9
+    assert rel(got.charge, ref["charge"]) < 1e-10 and rel(got.T, ref["T"]) < 1e-9 and dIo < 1e-9
     assert dI2 < 1e-2
 
 
