@@ -483,9 +483,9 @@ negf_status negf_server_stats(negf_server *s, negf_server_info *info);
  * host memory, its device memory and slot are freed, and it is queued again at the
  * back; when re-admitted it resumes from that state (the potential is rebuilt from
  * rho_in, self-energies are decimated again), so its results are bit-identical to an
- * uninterrupted run.  negf_server_evict(s, id) asks for one eviction (EINVAL if the
- * request is unknown or finished; it takes effect at the end of the current pass if
- * the request is running).  negf_server_set_time_slice(s, passes) makes the server
+ * uninterrupted run.  negf_server_evict(s, id) asks for one eviction at the end of the
+ * request's next pass (the current one if it is running; its first one after admission
+ * if it is queued); EINVAL if the request is unknown or has finished.  negf_server_set_time_slice(s, passes) makes the server
  * evict, whenever requests are waiting for admission, every running request that has
  * run `passes` passes since it was (re)admitted (0 = never, the default): round-robin
  * service under overload. */
