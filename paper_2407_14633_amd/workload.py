@@ -431,7 +431,7 @@ def serving_requests(n_req: int, seed: int = 5555, chiralities=(10, 13, 17, 20, 
 
     The drawn energy count ne sets the contour part (contour_frac of it) and the
     real-axis budget n_r = ne - n_c.  adaptive: the real axis is the semi-adaptive
-    grid (Section 3.3) with densities (0.5, 2, 0.5) x n_r kT / (E_max - E_min) nodes
+    grid (Section 3.3) with densities (1, 2, 1) x n_r kT / (E_max - E_min) nodes
     per kT in its three parts, guessed limits (mu_R, mu_L), rebuilt before the
     first pass and every grid_refresh passes; otherwise n_r fixed Gauss-Legendre
     nodes.  norm = 1, tol = 1e-6: stop when the output charge would move the
@@ -451,7 +451,7 @@ def serving_requests(n_req: int, seed: int = 5555, chiralities=(10, 13, 17, 20, 
             E_min, E_max = window(r.bias)
             kT = min(r.bias.kT_L, r.bias.kT_R)
             rho = n_r * kT / (E_max - E_min)
-            r.grid_density = (0.5 * rho, 2.0 * rho, 0.5 * rho)
+            r.grid_density = (rho, 2.0 * rho, rho)
             r.grid_limits = (min(r.bias.mu_L, r.bias.mu_R), max(r.bias.mu_L, r.bias.mu_R))
             r.grid_refresh = grid_refresh
         else:
