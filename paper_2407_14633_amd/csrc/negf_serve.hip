@@ -498,9 +498,11 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
     // per-request NEGF flags (ST_NOCONV: decimation; ST_BAD / ST_NOROOM: bad result)
     std::vector<ScJob*> keep, evict;
     bool waiting;
+    int slice;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         waiting = !S->pending.empty();
+        slice = S->slice;
     }
     const double t_now = now_ms();
     for (size_t r = 0; r < S->running.size(); ++r) {
@@ -525,7 +527,7 @@ negf_status server_pass(negf_server* S, std::vector<ScJob*>& admitted) {
             finish_job(S, j, NEGF_ENOCONV);
         } else if (j->deadline_ms > 0 && t_now - j->t_submit > j->deadline_ms) {
             finish_job(S, j, NEGF_ETIMEDOUT);
-        } else if (ask || (S->slice > 0 && waiting && j->passes - j->admitted_pass >= S->slice)) {
+        } else if (ask || (slice > 0 && waiting && j->passes - j->admitted_pass >= slice)) {
             evict.push_back(j);
         } else {
             keep.push_back(j);
