@@ -234,7 +234,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,   &w->iters, &w->status,
                         &w->coef_c, &w->coef_r,   &w->T,       &w->gr,      &w->ad,    &w->part, &w->Trl, &w->amax,
                         &w->store_f, &w->store_b, &w->scratch, &w->flags, &w->fp64_spans, &w->fp64_first,
-                        &w->fp64_all, &w->fp64_ctl};
+                        &w->fp64_all, &w->fp64_ctl, &w->cscale};
         for (DBuf* b : bufs) *b = DBuf{};
         w->arena_off = 0;
         w->last_tables.clear();
@@ -612,6 +612,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         TRY(grow(w, w->fp64_spans, fp64_max * sizeof(negf::Span)));
         TRY(grow(w, w->fp64_first, (fp64_max + 1) * sizeof(int)));
         TRY(grow(w, w->fp64_ctl, groups.size() * 2 * sizeof(int)));
+        TRY(grow(w, w->cscale, (size_t)n_jobs * sizeof(double)));
     }
 
     // ---- tables: one image [JobDesc][RedJob][Span][first], uploaded only when it
@@ -656,6 +657,7 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
 
     const negf::Span* cur_all = nullptr;   // node list of the group being recomputed
     bool side_open = false;                 // a contour-diagonal launch on the side stream is not joined yet
+    bool cscale_done = false;
     for (size_t li = 0; li < launches.size(); ++li) {
         const Launch& L = launches[li];
         const Group& g = groups[L.group];
@@ -668,8 +670,14 @@ negf_status enqueue(negf_workspace* w, int n_jobs, const negf_job* jobs, hipStre
         if (L.fp64 == 1) {   // list of the group's nodes to recompute; the cursor is reset
             int* ctl = d_fp64_ctl + 2 * L.group;
             hipLaunchKernelGGL(negf::k_fill_int, dim3(1), dim3(64), 0, s, ctl + 1, 1, 0);
+            if (!cscale_done) {   // every job's lead columns are done: its current scale
+                hipLaunchKernelGGL(negf::k_cur_scale, dim3(n_jobs), dim3(64), 0, s, d_jobs, d_red,
+                                   static_cast<double*>(w->cscale.p));
+                cscale_done = true;
+            }
             hipLaunchKernelGGL(negf::k_fp64_list, dim3(1), dim3(1024), 0, s, d_jobs, d_red, d_spans + L.span_at,
-                               d_nfirst + L.first_at, L.n_spans, g.L->B, d_fp64_all + L.cap, ctl);
+                               d_nfirst + L.first_at, L.n_spans, g.L->B, d_fp64_all + L.cap, ctl,
+                               static_cast<const double*>(w->cscale.p));
             cur_all = d_fp64_all + L.cap;
             continue;
         }
@@ -835,7 +843,7 @@ void ws_destroy(negf_workspace* w) {
     }
     DBuf* bufs[] = {&w->tables, &w->counters, &w->z,       &w->sigma,  &w->iters,      &w->status,
                     &w->coef_c, &w->coef_r,   &w->T,       &w->gr,     &w->ad,         &w->part, &w->Trl, &w->amax,
-                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc, &w->fp64_spans, &w->fp64_first, &w->fp64_all, &w->fp64_ctl,
+                    &w->store_f, &w->store_b, &w->scratch, &w->flags,  &w->in_zc,      &w->in_wc, &w->fp64_spans, &w->fp64_first, &w->fp64_all, &w->fp64_ctl, &w->cscale,
                     &w->in_Er,  &w->in_wr,    &w->out_charge, &w->out_T, &w->out_cur};
     for (DBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);

@@ -70,6 +70,7 @@ struct negf_workspace {
     size_t store_cap = 0;     // bytes per recursion store direction; 0 = default
     size_t default_store_cap = (size_t)8 << 30;   // set at creation from the free HBM
     int cus = 0;
+    DBuf cscale;              // FP32-bulk: per-job current scale for the recomputation test
     DBuf tables, counters, z, sigma, iters, status, coef_c, coef_r, T, gr, ad, part, store_f, store_b, scratch,
         flags, in_zc, in_wc, in_Er, in_wr, out_charge, out_T, out_cur, fp64_spans, fp64_first, Trl, amax, fp64_all, fp64_ctl;
     std::vector<char> last_tables;   // host image of `tables` (re-uploaded only when it changes)

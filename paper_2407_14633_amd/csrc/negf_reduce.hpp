@@ -195,6 +195,31 @@ __global__ __launch_bounds__(64) void k_current(const RedJob* jobs) {
 #define NEGF_FP32_QTOL 1e-7
 #endif
 
+// Current a node's transmission may move, relative to its job's current scale,
+// before its FP32 result is replaced.
+#ifndef NEGF_FP32_ITOL
+#define NEGF_FP32_ITOL 1e-6
+#endif
+
+// FP32-bulk: per job, the scale of its current, sum_q |w_q (f_L - f_R)(E_q) T_q| over
+// its real-axis nodes, in a fixed order (one wavefront per job).
+__global__ __launch_bounds__(64) void k_cur_scale(const JobDesc* jobs, const RedJob* red, double* scale) {
+    const RedJob& R = red[blockIdx.x];
+    const JobDesc& J = jobs[blockIdx.x];
+    __shared__ double s[64];
+    const int l = threadIdx.x;
+    double acc = 0.0;
+    for (int q = l; q < R.n_r; q += 64)
+        acc += fabs(R.w_r[q] * fermi_diff(R.E_r[q], R.mu_L, R.kT_L, R.mu_R, R.kT_R) * J.Tout[q]);
+    s[l] = acc;
+    __syncthreads();
+    for (int d = 32; d > 0; d >>= 1) {
+        if (l < d) s[l] += s[l + d];
+        __syncthreads();
+    }
+    if (l == 0) scale[blockIdx.x] = s[0];
+}
+
 // FP32-bulk, after the lead columns of every chunk of one kernel group: the
 // real-axis nodes to recompute in FP64.  A node is taken when the lead columns
 // marked it (ST_FP64), or when its two transmissions disagree by more than its
@@ -202,14 +227,16 @@ __global__ __launch_bounds__(64) void k_current(const RedJob* jobs) {
 // from the left one (backward recursion), and they agree up to O(eta) unless an
 // FP32 recursion lost digits; with r = |T_LR - T_RL| / max(T_LR, T_RL) and the
 // node's largest charge term c = g_s (|w|/pi) (f_L max_i A_L,ii + f_R max_i A_R,ii)
-// the node is taken when c sqrt(r) > NEGF_FP32_QTOL (sqrt(r): the spectral
+// the node is taken when c sqrt(r) > NEGF_FP32_QTOL, or when |w (f_L - f_R)| |T_LR - T_RL|
+// exceeds NEGF_FP32_ITOL of the job's sum_q |w_q (f_L - f_R) T_q| (sqrt(r): the spectral
 // densities were measured to be off by up to ~100 r on the nanotube workloads).
 // The taken nodes are listed in node order as one-node spans whose `off` is the
 // running sum of their FP64 store sizes (N b^2 elements each); *count receives
 // their number.  col[0..n_col) are the group's column spans, col_first their node
 // prefix.  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const RedJob* red, const Span* col,
-                                                   const int* col_first, int n_col, int B, Span* all, int* count) {
+                                                   const int* col_first, int n_col, int B, Span* all, int* count,
+                                                   const double* cscale) {
     __shared__ long long s_sz[1024];
     __shared__ int s_ct[1024];
     __shared__ long long s_base;
@@ -245,7 +272,10 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
                              (fermi_real(E, R.mu_L, R.kT_L) * J.amax[2 * ir] +
                               fermi_real(E, R.mu_R, R.kT_R) * J.amax[2 * ir + 1]);
             const bool recip = !(c * sqrt(r) <= NEGF_FP32_QTOL);
-            const bool take = J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e] & ST_FP64) || recip));
+            // and when the mismatch could move the job's current by more than NEGF_FP32_ITOL of its scale
+            const double wf = fabs(R.w_r[ir] * fermi_diff(E, R.mu_L, R.kT_L, R.mu_R, R.kT_R));
+            const bool cur = wf * fabs(t1 - t2) > NEGF_FP32_ITOL * cscale[job];
+            const bool take = J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e] & ST_FP64) || recip || cur));
             if (take) {
                 ct = 1;
                 sz = (long long)J.N * B * B;
