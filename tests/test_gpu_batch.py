@@ -308,3 +308,25 @@ def test_batch_long_23_tube_matches_oracle(gpu_lib):
             assert rel(g.T, ref["T"]) < 1e-9
         for d in devs:
             d.close()
+
+
+def test_fp32_bulk_batch_within_contract(gpu_lib):
+    """The 64-device batch (ring sizes 10-23, 200-2000 rings, 512-4096 nodes) in FP32-bulk
+    against the same batch in FP64 (equal to the oracle by the tests above): every job's
+    charge and, for jobs carrying at least 1e-3 of the largest current, its current
+    within 1e-5."""
+    negf = gpu_lib
+    ps = W.batch_problems(64, 4040)
+    res = {}
+    for prec in (negf.FP64, negf.FP32_BULK):
+        devs = open_devices(negf, ps, [prec] * len(ps))
+        with negf.Workspace() as ws:
+            res[prec] = ws.solve([negf.Job(d, p.bias, p.grid) for d, p in zip(devs, ps)])
+        for d in devs:
+            d.close()
+    a, b = res[negf.FP64], res[negf.FP32_BULK]
+    eq = [rel(y.charge, x.charge) for x, y in zip(a, b)]
+    big = max(abs(x.current) for x in a)
+    ei = [abs(y.current - x.current) / abs(x.current) for x, y in zip(a, b) if abs(x.current) >= 1e-3 * big]
+    say("FP32-bulk batch: worst charge", max(eq), "worst current", max(ei), "over", len(ei), "jobs")
+    assert max(eq) < 1e-5 and max(ei) < 1e-5
