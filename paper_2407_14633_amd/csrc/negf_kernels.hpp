@@ -1214,6 +1214,7 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
     __shared__ cx<T> s_stage[G][B * B];
     __shared__ cx<T> s_gam[G][B * B];
     __shared__ double s_chk[G][4][B];
+    __shared__ double s_lam[G][B];   // eigenvalues of a circulant Gamma (FP64 stores)
 
     const int lane = threadIdx.x;
     const int gi = lane / B;
@@ -1281,7 +1282,51 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int j = 0; j < B; ++j) { const cx<TS> v = gload(w0 + j); wr[j] = v.re; wi[j] = v.im; }
         }
+        // A circulant Gamma = sum_q lambda_q v_q v_q^H (v_q[j] = e^{2 pi i q j / B} / sqrt(B),
+        // lambda_q = sum_d Gamma[0][d] e^{2 pi i q d / B}): with W' = W F^H (columns in the
+        // ring Fourier basis, F^H[k][q] = v_q[k]) the propagation W' <- -P W' is unchanged
+        // and diag(W Gamma W^H)_rr = sum_q lambda_q |W'[r][q]|^2, B terms instead of B^2.
+        // Used with FP64 stores (the FP32 checks look at the entries of W itself).
+        const bool four = sizeof(TS) == 8 && gcirc;
         stage_row<T, B>(wr, wi, St, r, act);
+        if (four) {
+            wave_sync();   // Gamma and the rows of W are in LDS
+            {
+                double lr = 0.0;   // lambda_r (real: Gamma is Hermitian)
+                for (int d = 0; d < B; ++d) {
+                    double sn, cs;
+                    sincospi(2.0 * (double)((r * d) % B) / B, &sn, &cs);
+                    const cx<T> c = Gm[d];
+                    lr = fma((double)c.re, cs, fma(-(double)c.im, sn, lr));
+                }
+                if (act) s_lam[gsafe][r] = lr;
+            }
+            T twr[B], twi[B];   // e^{2 pi i m / B}
+#pragma unroll
+            for (int m = 0; m < B; ++m) {
+                double sn, cs;
+                sincospi(2.0 * m / B, &sn, &cs);
+                twr[m] = cs;
+                twi[m] = sn;
+            }
+            const T sc = T(1) / sqrt(T(B));
+            const cx<T>* row = St + r * B;   // this lane's row of W
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                T ar = T(0), ai = T(0);
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    const int m = (q * k) % B;
+                    const cx<T> x = row[k];
+                    ar = fma(x.re, twr[m], fma(-x.im, twi[m], ar));
+                    ai = fma(x.re, twi[m], fma(x.im, twr[m], ai));
+                }
+                wr[q] = ar * sc;
+                wi[q] = ai * sc;
+            }
+            wave_sync();
+            stage_row<T, B>(wr, wi, St, r, act);   // the rows of W'
+        }
         wave_sync();
         double* aout = reinterpret_cast<double*>(J.a_diag) + ((size_t)(act ? ir : 0) * 2 + lead) * N * B;
         // this row's max |W_rj| and range of A_rr along the chain, kept in LDS (the
@@ -1309,8 +1354,18 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
             // ring-mode decimation) only Gamma's first row is read.
             int goff = gsafe * B * B;
             asm volatile("" : "+v"(goff));
-            const T acc = gcirc ? row_quad_circ<T, B>(wr, wi, &s_gam[0][0] + goff)
-                                : row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
+            T acc;
+            if (four) {   // sum_q lambda_q |W'[r][q]|^2
+                int loff = gsafe * B;
+                asm volatile("" : "+v"(loff));
+                const double* lam = &s_lam[0][0] + loff;
+                acc = T(0);
+#pragma unroll
+                for (int q = 0; q < B; ++q) acc = fma(T(lam[q]), fma(wr[q], wr[q], wi[q] * wi[q]), acc);
+            } else {
+                acc = gcirc ? row_quad_circ<T, B>(wr, wi, &s_gam[0][0] + goff)
+                            : row_quad_pipe<T, B>(wr, wi, &s_gam[0][0] + goff);
+            }
             if (act) {
                 gstore_s(aout + (size_t)n * B + r, acc);
                 if (s == 0) {
@@ -1338,7 +1393,16 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         double t = 0.0;
         {
             T vr[B], vi[B];
-            row_mul<T, B>(wr, wi, Gm, vr, vi);
+            if (four) {   // (W' diag(lambda))[r][q]; St holds the rows of W'
+#pragma unroll
+                for (int q = 0; q < B; ++q) {
+                    const T l = T(s_lam[gsafe][q]);
+                    vr[q] = l * wr[q];
+                    vi[q] = l * wi[q];
+                }
+            } else {
+                row_mul<T, B>(wr, wi, Gm, vr, vi);
+            }
             if (act) {
                 const cx<double>* sl = J.sigma + ((size_t)e * 2 + (1 - lead)) * B * B;
                 for (int jp = 0; jp < B; ++jp) {
