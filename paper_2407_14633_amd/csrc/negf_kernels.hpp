@@ -1286,8 +1286,9 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
         // lambda_q = sum_d Gamma[0][d] e^{2 pi i q d / B}): with W' = W F^H (columns in the
         // ring Fourier basis, F^H[k][q] = v_q[k]) the propagation W' <- -P W' is unchanged
         // and diag(W Gamma W^H)_rr = sum_q lambda_q |W'[r][q]|^2, B terms instead of B^2.
-        // Used with FP64 stores (the FP32 checks look at the entries of W itself).
-        const bool four = sizeof(TS) == 8 && gcirc;
+        // The FP32 size check then uses sqrt(2) |W_r|_2, the same in both bases and never
+        // below max_j (|Re W_rj| + |Im W_rj|).
+        const bool four = gcirc;
         stage_row<T, B>(wr, wi, St, r, act);
         if (four) {
             wave_sync();   // Gamma and the rows of W are in LDS
@@ -1344,9 +1345,16 @@ __global__ __launch_bounds__(64, NEGF_RGF_WAVES) __attribute__((amdgpu_waves_per
 #pragma unroll
                 for (int j = 0; j < B; ++j) { const cx<TS> v = gload(p + j); pr[j] = -T(v.re); pi[j] = -T(v.im); }
             }
-            double wm = 0.0;
+            double wm = 0.0;   // read by the FP32 checks only
+            if (sizeof(TS) == 4 && four) {
+                double s2 = 0.0;
 #pragma unroll
-            for (int j = 0; j < B; ++j) wm = fmax(wm, fabs(wr[j]) + fabs(wi[j]));
+                for (int j = 0; j < B; ++j) s2 = fma(wr[j], wr[j], fma(wi[j], wi[j], s2));
+                wm = sqrt(2.0 * s2);
+            } else {
+#pragma unroll
+                for (int j = 0; j < B; ++j) wm = fmax(wm, fabs(wr[j]) + fabs(wi[j]));
+            }
             // diag(W Gamma W^H)_rr = Re sum_j (W Gamma)[r][j] conj(W[r][j]).  Gamma does not
             // change along the chain; its offset is made opaque each step so that its
             // B*B reads are not hoisted out of the loop into (spilled) registers.
