@@ -400,3 +400,39 @@ def test_fp32_bulk_recomputed_nodes_equal_fp64(gpu_lib):
     assert not np.array_equal(none.al_diag, r64.al_diag)
     # T_RL equals T_LR up to O(eta) in FP64
     assert np.max(np.abs(r64.T - r64.T_rl) / np.maximum(r64.T, 1e-300)) < 1e-4
+
+
+@pytest.mark.parametrize("periods,b,N", [((1, 1), 9, 6), ((2, 1), 17, 6), ((1, 2), 24, 2)])
+def test_circulant_lead_columns_both_precisions(gpu_lib, periods, b, N):
+    """Lead columns of devices with ring-circulant leads run in the ring Fourier basis
+    (Gamma diagonal there): random complex circulant leads at several ring sizes, full
+    solves in FP64 and FP32-bulk against the oracle (Eqs. 4-5).  The oracle's dense
+    decimation is only as good as the lead's own conditioning at each node (its change
+    under 2e-16 input jitter, up to 7e-10 here at eta = 1e-2), so the FP64 gates are
+    1e-10 (charge, current) and 1e-9 (T) or ten times that sensitivity if larger.
+    At b = 24 two rings (one coupling block): the coupling table of dense random
+    couplings holds one distinct 24-wide block."""
+    dev = _random_circulant_device(N, b, seed=70 + b, periods=periods)
+    rng = np.random.default_rng(300 + b)
+    U = rng.uniform(-0.2, 0.2, dev.n_rings * dev.b)
+    bias = W.Bias(0.15, -0.1, 0.05, 0.04)
+    grid = W.nonequilibrium_grid(W.gershgorin_lower(dev, U) - 1.0, bias, 5, 9)
+    eta = 1e-2
+    p = W.Problem("circ-col", dev, U, 0.03, -0.05, bias, grid, eta=eta)
+    sens = 0.0
+    for ld, Ul in ((dev.left, p.U_left), (dev.right, p.U_right)):
+        for z in list(grid.z_c) + [e + 1j * eta for e in grid.E_r]:
+            sig, _ = O.self_energy(ld, Ul, z)
+            sens = max(sens, _oracle_sensitivity(ld, Ul, z, sig, trials=3))
+    ref = O.solve(p)
+    got = gpu_lib.solve_problem(p)
+    e_q, e_t = rel(got.charge, ref["charge"]), rel(got.T, ref["T"], floor=1e-12)
+    say("circulant columns fp64", periods, b, e_q, e_t, "oracle sensitivity", sens)
+    assert e_q < max(1e-10, 10 * sens)
+    assert e_t < max(1e-9, 10 * sens)
+    assert abs(got.current - ref["current"]) <= max(1e-10, 10 * sens) * abs(ref["current"]) + 1e-25
+    g32 = gpu_lib.solve_problem(p, precision=gpu_lib.FP32_BULK)
+    e_q = rel(g32.charge, ref["charge"])
+    e_c = abs(g32.current - ref["current"]) / abs(ref["current"])
+    say("circulant columns fp32-bulk", periods, b, e_q, e_c, g32.fp64_nodes)
+    assert e_q < FP32_BULK_BOUND and e_c < FP32_BULK_BOUND
