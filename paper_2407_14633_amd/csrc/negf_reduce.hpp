@@ -237,11 +237,11 @@ __global__ __launch_bounds__(64) void k_cur_scale(const JobDesc* jobs, const Red
 __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const RedJob* red, const Span* col,
                                                    const int* col_first, int n_col, int B, Span* all, int* count,
                                                    const double* cscale) {
-    __shared__ long long s_sz[1024];
-    __shared__ int s_ct[1024];
+    __shared__ long long s_wsz[16];   // per-wavefront totals of a chunk
+    __shared__ int s_wct[16];
     __shared__ long long s_base;
     __shared__ int s_seen;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) {
         s_base = 0;
         s_seen = 0;
@@ -281,22 +281,33 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
                 sz = (long long)J.N * B * B;
             }
         }
-        s_sz[tid] = sz;
-        s_ct[tid] = ct;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {   // inclusive scans of sizes and counts
-            const long long a = tid >= d ? s_sz[tid - d] : 0;
-            const int c = tid >= d ? s_ct[tid - d] : 0;
-            __syncthreads();
-            s_sz[tid] += a;
-            s_ct[tid] += c;
-            __syncthreads();
+        const long long b0 = s_base;   // list so far (updated below, after every thread has read it)
+        const int c0 = s_seen;
+        // inclusive scans of sizes and counts in node order: within the wavefront by
+        // shuffles, then over the totals of the wavefronts before this one
+        long long xs = sz;
+        int xc = ct;
+        for (int d = 1; d < 64; d <<= 1) {
+            const long long ys = __shfl_up(xs, d, 64);
+            const int yc = __shfl_up(xc, d, 64);
+            if (lane >= d) {
+                xs += ys;
+                xc += yc;
+            }
         }
-        if (ct) all[s_seen + s_ct[tid] - 1] = Span{job, e, 1, 0, s_base + s_sz[tid] - sz};
+        if (lane == 63) {
+            s_wsz[wv] = xs;
+            s_wct[wv] = xc;
+        }
         __syncthreads();
-        if (tid == 0) {
-            s_base += s_sz[1023];
-            s_seen += s_ct[1023];
+        for (int k = 0; k < wv; ++k) {
+            xs += s_wsz[k];
+            xc += s_wct[k];
+        }
+        if (ct) all[c0 + xc - 1] = Span{job, e, 1, 0, b0 + xs - sz};
+        if (tid == 1023) {
+            s_base = b0 + xs;
+            s_seen = c0 + xc;
         }
         __syncthreads();
     }
