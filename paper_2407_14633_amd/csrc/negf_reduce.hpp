@@ -248,22 +248,37 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
     }
     __syncthreads();
     const int total = col_first[n_col];
-    for (int base = 0; base < total; base += 1024) {
-        const int t = base + tid;
-        int job = 0, e = 0, ct = 0;
-        long long sz = 0;
-        if (t < total) {
-            int lo = 0, hi = n_col;   // col_first[lo] <= t < col_first[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (col_first[mid] <= t) lo = mid; else hi = mid;
-            }
-            const Span sp = col[lo];
-            job = sp.job;
-            e = sp.e0 + (t - col_first[lo]);
-            const JobDesc& J = jobs[job];
-            const RedJob& R = red[job];
-            const int ir = e - J.n_c;
+    int top = 1;   // largest power of two <= n_col
+    while (2 * top <= n_col) top *= 2;
+    constexpr int PER = 4;   // consecutive nodes per thread, their loads in flight together
+    for (int base = 0; base < total; base += 1024 * PER) {
+        const int t0 = base + PER * tid;
+        // span of each node: the largest lo with col_first[lo] <= t (a non-empty span),
+        // by a fixed number of halving steps so the searches of the PER nodes interleave
+        int lo[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) lo[k] = 0;
+        for (int step = top; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k)
+                if (lo[k] + step < n_col && col_first[lo[k] + step] <= t0 + k) lo[k] += step;
+        }
+        int job[PER], e[PER], ct[PER];
+        long long sz[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int t = t0 + k;
+            job[k] = 0;
+            e[k] = 0;
+            ct[k] = 0;
+            sz[k] = 0;
+            if (t >= total) continue;
+            const Span sp = col[lo[k]];
+            job[k] = sp.job;
+            e[k] = sp.e0 + (t - col_first[lo[k]]);
+            const JobDesc& J = jobs[job[k]];
+            const RedJob& R = red[job[k]];
+            const int ir = e[k] - J.n_c;
             const double t1 = J.Tout[ir], t2 = J.Trl[ir];
             const double tmax = fmax(fabs(t1), fabs(t2));
             const double r = tmax > 0.0 ? fabs(t1 - t2) / tmax : 0.0;
@@ -274,19 +289,27 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
             const bool recip = !(c * sqrt(r) <= NEGF_FP32_QTOL);
             // and when the mismatch could move the job's current by more than NEGF_FP32_ITOL of its scale
             const double wf = fabs(R.w_r[ir] * fermi_diff(E, R.mu_L, R.kT_L, R.mu_R, R.kT_R));
-            const bool cur = wf * fabs(t1 - t2) > NEGF_FP32_ITOL * cscale[job];
-            const bool take = J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e] & ST_FP64) || recip || cur));
+            const bool cur = wf * fabs(t1 - t2) > NEGF_FP32_ITOL * cscale[job[k]];
+            const bool take =
+                J.fp64_policy == 1 || (J.fp64_policy == 0 && ((J.status[e[k]] & ST_FP64) || recip || cur));
             if (take) {
-                ct = 1;
-                sz = (long long)J.N * B * B;
+                ct[k] = 1;
+                sz[k] = (long long)J.N * B * B;
             }
+        }
+        long long ts = 0;   // this thread's totals
+        int tc = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            ts += sz[k];
+            tc += ct[k];
         }
         const long long b0 = s_base;   // list so far (updated below, after every thread has read it)
         const int c0 = s_seen;
-        // inclusive scans of sizes and counts in node order: within the wavefront by
+        // inclusive scans of the thread totals in node order: within the wavefront by
         // shuffles, then over the totals of the wavefronts before this one
-        long long xs = sz;
-        int xc = ct;
+        long long xs = ts;
+        int xc = tc;
         for (int d = 1; d < 64; d <<= 1) {
             const long long ys = __shfl_up(xs, d, 64);
             const int yc = __shfl_up(xc, d, 64);
@@ -300,11 +323,18 @@ __global__ __launch_bounds__(1024) void k_fp64_list(const JobDesc* jobs, const R
             s_wct[wv] = xc;
         }
         __syncthreads();
-        for (int k = 0; k < wv; ++k) {
-            xs += s_wsz[k];
-            xc += s_wct[k];
+        for (int q = 0; q < wv; ++q) {
+            xs += s_wsz[q];
+            xc += s_wct[q];
         }
-        if (ct) all[c0 + xc - 1] = Span{job, e, 1, 0, b0 + xs - sz};
+        long long off = b0 + xs - ts;   // store offset and list slot of this thread's first taken node
+        int slot = c0 + xc - tc;
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (ct[k]) {
+                all[slot++] = Span{job[k], e[k], 1, 0, off};
+                off += sz[k];
+            }
         if (tid == 1023) {
             s_base = b0 + xs;
             s_seen = c0 + xc;
